@@ -1,0 +1,224 @@
+"""Seeded synthetic inputs: spectra, priors and request traces.
+
+This module is the simulated instrument.  It draws ground-truth peak
+parameters, evaluates the *generating* model with its own numpy code, adds
+noise and rounds the grid and the observations to float32-representable
+values (so that an FP32 consumer and an FP64 consumer read the same numbers).
+It holds none of the sampler's arithmetic, imports neither the HIP binding nor
+the CPU reference, and both of them read its output.
+
+The recipes stand in for the paper's measured and artificial spectra, which
+are not available: XPS-like spectra (N ~ 300-1000, up to ~10 peaks, Sec. III.A.2
+and III.B.2) and XRD-like Poisson patterns (N 1000-10000, Sec. III.A.1 and
+App. C).  Every draw uses ``numpy.random.default_rng(seed)`` with the data seed
+1000 * config + spectrum index.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+Prior = Tuple[str, float, float]   # ("uniform", lo, hi) | ("gamma", shape, rate) | ("normal", mean, sd) | ("fixed", v, 0)
+
+
+@dataclasses.dataclass
+class Spectrum:
+    x: np.ndarray
+    y: np.ndarray
+    peak_kind: str                    # "gauss" (A, mu, b=precision) | "pvoigt" (A, mu, sigma=HWHM, eta=Gaussian fraction)
+    bg_kind: str                      # "none" | "const" (b) | "linear" (c0, c1)
+    noise_kind: str                   # "gauss" (known sigma) | "poisson"
+    sigma: float
+    peak_prior: Sequence[Prior]
+    bg_prior: Sequence[Prior]
+    k_min: int
+    k_max: int
+    peak_prior_k: Optional[List[Sequence[Prior]]] = None
+    truth: Optional[dict] = None
+    uid: int = 0
+
+    @property
+    def n(self) -> int:
+        return len(self.x)
+
+
+def f32(a) -> np.ndarray:
+    """Round to the nearest float32 and return as float64."""
+    return np.asarray(a, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+# --- the simulated instrument: generating profiles (numpy, float64) --------------------
+
+def _gen_gauss(x, A, mu, b):
+    return A * np.exp(-0.5 * b * (x - mu) ** 2)
+
+
+def _gen_pvoigt(x, A, mu, s, eta):
+    g = np.exp(-np.log(2.0) * (x - mu) ** 2 / s ** 2)
+    lor = s ** 2 / (s ** 2 + (x - mu) ** 2)
+    return A * (eta * g + (1.0 - eta) * lor)
+
+
+def _synth(x, kind, peaks, bg=(0.0, 0.0)):
+    f = np.full_like(x, bg[0]) + bg[1] * x
+    for p in peaks:
+        f = f + (_gen_gauss(x, *p) if kind == "gauss" else _gen_pvoigt(x, *p))
+    return f
+
+
+# --- the five workloads ------------------------------------------------------------------
+
+GAUSS_PRIORS: List[Prior] = [("gamma", 2.0, 1.0), ("uniform", 0.0, 10.0), ("gamma", 2.0, 0.25)]
+PV_PRIORS: List[Prior] = [("gamma", 2.0, 1.0), ("uniform", 0.0, 10.0), ("gamma", 2.0, 4.0), ("uniform", 0.0, 1.0)]
+
+
+def config1(index: int = 0) -> Spectrum:
+    """XPS-like: N=201 on [0,10], 3 Gaussian peaks (A~U[0.5,2], mu~U[2,8], SD~U[0.2,0.8],
+    precision b=1/SD^2), sigma=0.05, candidates K=1..4."""
+    rng = np.random.default_rng(1000 * 1 + index)
+    x = f32(10.0 * np.arange(201) / 200.0)
+    A = rng.uniform(0.5, 2.0, 3)
+    mu = rng.uniform(2.0, 8.0, 3)
+    sd = rng.uniform(0.2, 0.8, 3)
+    peaks = [(A[k], mu[k], 1.0 / sd[k] ** 2) for k in range(3)]
+    sigma = 0.05
+    y = f32(_synth(x, "gauss", peaks) + sigma * rng.standard_normal(x.size))
+    return Spectrum(x, y, "gauss", "none", "gauss", sigma, GAUSS_PRIORS, [], 1, 4,
+                    truth={"K": 3, "peaks": peaks}, uid=1000 + index)
+
+
+def config2(index: int = 0) -> Spectrum:
+    """XPS-like at GPU scale: N=1001 on [0,10], 5 pseudo-Voigt peaks (A~U[0.5,2], mu~U[2,8],
+    HWHM~U[0.2,0.8], eta~U[0,1]) on a linear background (c0~U[0,0.5], c1~U[-0.05,0.05]),
+    sigma=0.02, candidates K=1..8."""
+    rng = np.random.default_rng(1000 * 2 + index)
+    x = f32(10.0 * np.arange(1001) / 1000.0)
+    A = rng.uniform(0.5, 2.0, 5)
+    mu = rng.uniform(2.0, 8.0, 5)
+    s = rng.uniform(0.2, 0.8, 5)
+    eta = rng.uniform(0.0, 1.0, 5)
+    c0 = rng.uniform(0.0, 0.5)
+    c1 = rng.uniform(-0.05, 0.05)
+    peaks = [(A[k], mu[k], s[k], eta[k]) for k in range(5)]
+    sigma = 0.02
+    y = f32(_synth(x, "pvoigt", peaks, (c0, c1)) + sigma * rng.standard_normal(x.size))
+    bgp = [("uniform", -0.5, 1.0), ("uniform", -0.1, 0.1)]
+    return Spectrum(x, y, "pvoigt", "linear", "gauss", sigma, PV_PRIORS, bgp, 1, 8,
+                    truth={"K": 5, "peaks": peaks, "bg": (c0, c1)}, uid=2000 + index)
+
+
+def config3(index: int = 0) -> Spectrum:
+    """XRD-like: N=4096 on 2theta in [10,90], 16 narrow pseudo-Voigt peaks (A~U[1e3,1e4],
+    mu~U[12,88], HWHM~U[0.05,0.3], eta~U[0,1]) on a constant background b=100, Poisson
+    counts, candidates K=12..20."""
+    rng = np.random.default_rng(1000 * 3 + index)
+    x = f32(10.0 + 80.0 * np.arange(4096) / 4095.0)
+    A = rng.uniform(1e3, 1e4, 16)
+    mu = rng.uniform(12.0, 88.0, 16)
+    s = rng.uniform(0.05, 0.3, 16)
+    eta = rng.uniform(0.0, 1.0, 16)
+    peaks = [(A[k], mu[k], s[k], eta[k]) for k in range(16)]
+    f = _synth(x, "pvoigt", peaks, (100.0, 0.0))
+    y = rng.poisson(f).astype(np.float64)
+    ymax, ymin, ymed = float(y.max()), float(y.min()), float(np.median(y))
+    pp = [("gamma", 4.0, 4.0 / (ymax - ymin)), ("uniform", 10.0, 90.0), ("gamma", 2.0, 2.0 / 0.175),
+          ("uniform", 0.0, 1.0)]
+    bgp = [("uniform", 0.5 * ymed, 1.5 * ymed)]
+    return Spectrum(x, y, "pvoigt", "const", "poisson", 0.0, pp, bgp, 12, 20,
+                    truth={"K": 16, "peaks": peaks, "bg": (100.0,)}, uid=3000 + index)
+
+
+def config4(n_spectra: int = 512, index0: int = 0) -> List[Spectrum]:
+    """Batch of independent spectra: N_s~U{200..4000} on [0,10], kind Gaussian or
+    pseudo-Voigt 50/50, K_true~U{1..6} with the config-1 / config-2 ranges, no background,
+    sigma_s~U[0.01,0.1], candidates K=1..8."""
+    out = []
+    for s_idx in range(index0, index0 + n_spectra):
+        rng = np.random.default_rng(1000 * 4 + s_idx)
+        n = int(rng.integers(200, 4001))
+        kind = "gauss" if rng.uniform() < 0.5 else "pvoigt"
+        kt = int(rng.integers(1, 7))
+        sigma = float(rng.uniform(0.01, 0.1))
+        x = f32(10.0 * np.arange(n) / (n - 1))
+        A = rng.uniform(0.5, 2.0, kt)
+        mu = rng.uniform(2.0, 8.0, kt)
+        w = rng.uniform(0.2, 0.8, kt)
+        if kind == "gauss":
+            peaks = [(A[k], mu[k], 1.0 / w[k] ** 2) for k in range(kt)]
+            pri = GAUSS_PRIORS
+        else:
+            eta = rng.uniform(0.0, 1.0, kt)
+            peaks = [(A[k], mu[k], w[k], eta[k]) for k in range(kt)]
+            pri = PV_PRIORS
+        y = f32(_synth(x, kind, peaks) + sigma * rng.standard_normal(n))
+        out.append(Spectrum(x, y, kind, "none", "gauss", sigma, pri, [], 1, 8,
+                            truth={"K": kt, "peaks": peaks}, uid=4000 + s_idx))
+    return out
+
+
+def config5_trace(n_arrivals: int = 2000, rate: float = 200.0, seed: int = 5000):
+    """Poisson(rate) arrival times with a 70/30 mix of config-1 and config-2 shaped requests.
+    Returns a list of (arrival_time_s, Spectrum)."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, n_arrivals))
+    kinds = rng.uniform(size=n_arrivals) < 0.7
+    out = []
+    for i in range(n_arrivals):
+        sp = config1(10000 + i) if kinds[i] else config2(10000 + i)
+        sp.uid = 50000 + i
+        out.append((float(t[i]), sp))
+    return out
+
+
+# --- small problems with known answers (test inputs) -------------------------------------
+
+def linear_gaussian(n: int = 40, K: int = 2, sigma: float = 0.3, m0: float = 0.5, s0: float = 1.0,
+                    seed: int = 7) -> Spectrum:
+    """Gaussian peaks with FIXED centres and precisions and Normal(m0, s0) amplitudes: the
+    model is linear in the amplitudes, so the evidence has a closed form."""
+    rng = np.random.default_rng(seed)
+    x = f32(np.linspace(0.0, 10.0, n))
+    mus = f32(np.linspace(2.5, 7.5, K))
+    bs = f32(np.full(K, 1.5))
+    amps = rng.normal(m0, s0, K)
+    y = f32(_synth(x, "gauss", [(amps[k], mus[k], bs[k]) for k in range(K)]) + sigma * rng.standard_normal(n))
+    rows = [[("normal", m0, s0), ("fixed", float(mus[k]), 0.0), ("fixed", float(bs[k]), 0.0)] for k in range(K)]
+    return Spectrum(x, y, "gauss", "none", "gauss", sigma, rows[0], [], K, K, peak_prior_k=rows,
+                    truth={"K": K, "amps": amps, "mus": mus, "bs": bs, "m0": m0, "s0": s0})
+
+
+def k1_problem(n: int = 15, sigma: float = 0.4, seed: int = 11) -> Spectrum:
+    """One Gaussian peak with the config-1 priors on a short noisy grid (broad posterior)."""
+    rng = np.random.default_rng(seed)
+    x = f32(np.linspace(0.0, 10.0, n))
+    y = f32(_synth(x, "gauss", [(1.5, 4.3, 0.8)]) + sigma * rng.standard_normal(n))
+    return Spectrum(x, y, "gauss", "none", "gauss", sigma, GAUSS_PRIORS, [], 1, 1,
+                    truth={"K": 1, "peaks": [(1.5, 4.3, 0.8)]})
+
+
+def random_spectrum(rng: np.random.Generator, n: int, peak_kind: str, bg_kind: str, noise_kind: str,
+                    k_true: int = 3) -> Spectrum:
+    """Generic seeded spectrum for parity tests of the energy: ragged N, any model kind."""
+    x = f32(np.sort(rng.uniform(0.0, 10.0, n)))
+    A = rng.uniform(0.5, 2.0, k_true) * (300.0 if noise_kind == "poisson" else 1.0)
+    mu = rng.uniform(1.0, 9.0, k_true)
+    if peak_kind == "gauss":
+        peaks = [(A[k], mu[k], rng.uniform(2.0, 25.0)) for k in range(k_true)]
+    else:
+        peaks = [(A[k], mu[k], rng.uniform(0.1, 0.8), rng.uniform()) for k in range(k_true)]
+    bg = {"none": (0.0, 0.0), "const": (50.0 if noise_kind == "poisson" else 0.2, 0.0),
+          "linear": (50.0 if noise_kind == "poisson" else 0.2, 0.03)}[bg_kind]
+    f = _synth(x, peak_kind, peaks, bg)
+    if noise_kind == "poisson":
+        y = rng.poisson(np.maximum(f, 0.0)).astype(np.float64)
+        sigma = 0.0
+    else:
+        sigma = 0.05
+        y = f32(f + sigma * rng.standard_normal(n))
+    pp = GAUSS_PRIORS if peak_kind == "gauss" else PV_PRIORS
+    bgp = {"none": [], "const": [("uniform", 0.0, 100.0)],
+           "linear": [("uniform", -1.0, 100.0), ("uniform", -1.0, 1.0)]}[bg_kind]
+    return Spectrum(x, y, peak_kind, bg_kind, noise_kind, sigma, pp, bgp, 1, 4,
+                    truth={"K": k_true, "peaks": peaks, "bg": bg})
