@@ -1,0 +1,165 @@
+#!/usr/bin/env python3
+"""Benchmark of the SMC sampler's hot path on one MI355X.
+
+One step = one whole run of the tempered sampler for one spectrum and every
+candidate K: stage-0 prior draws and energies, then every tempering stage
+(bisection, weights, evidence, resampling, step sizes, MH move) until each K
+has made its final move at beta = 1.  The workload is the GPU-scale XPS-like
+spectrum: N = 1001 points, 5 pseudo-Voigt peaks on a linear background,
+sigma = 0.02, candidates K = 1..8, P = 65536 particles per K, waste-free with
+n = 16.  The spectrum is uploaded once; each step restarts from stage 0 on the
+resident data with a new seed, so the timed region holds device work only.
+
+value = particle*point likelihood evaluations per second: every likelihood
+evaluation (one per particle at stage 0, one per Metropolis proposal inside
+the prior's support) covers N points.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Per particle*point operation counts of the move kernel's inner loop (one
+# pseudo-Voigt profile evaluation and the Gaussian-noise residual per point per
+# proposal): t = x - mu, t^2, c t^2, s2 + t^2, aG e, fma(aL, l, .), r = D - g,
+# fma(r, r, acc) -> 8 VALU, plus exp2 and rcp -> 2 transcendental.
+VALU_PER_UNIT = {("pvoigt", "gauss"): 8, ("gauss", "gauss"): 6}
+TRANS_PER_UNIT = {("pvoigt", "gauss"): 2, ("gauss", "gauss"): 1}
+# Issue cost of one transcendental relative to one VALU instruction on gfx950,
+# measured with a throughput microbenchmark (see the design notes).
+TRANS_COST = float(os.environ.get("SMC_TRANS_COST", "2.0"))
+# MI355X: 256 CUs x 4 SIMD x 16 lanes per clock x 2.4 GHz = 39.3e12 lane-instructions/s
+PEAK_LANE_OPS = 256 * 64 * 2.4e9
+
+
+def cpu_baseline(spec, K, seconds_target=12.0):
+    """The FP64 reference's move (its hot loop) on a bounded sample of the same workload."""
+    import oracle
+    opr = oracle.Problem(spec)
+    threads = oracle.num_threads()
+    M = 8 * threads
+    n = 16
+    th, E = oracle.init(opr, K, M, seed=1, uid=spec.uid)
+    step = 0.05 * th.std(axis=0)
+    t0 = time.perf_counter()
+    _, _, _, ne = oracle.move(opr, K, th, E, step, 1e-3, n, True, 1, spec.uid, 1, return_evals=True)
+    dt = time.perf_counter() - t0
+    # scale the sample to the target duration if it was too short
+    if dt < 0.25 * seconds_target:
+        reps = max(1, int(seconds_target / max(dt, 1e-3)) // 2)
+        M2 = min(M * reps, 64 * threads * 8)
+        th, E = oracle.init(opr, K, M2, seed=1, uid=spec.uid)
+        t0 = time.perf_counter()
+        _, _, _, ne = oracle.move(opr, K, th, E, step, 1e-3, n, True, 1, spec.uid, 1, return_evals=True)
+        dt = time.perf_counter() - t0
+        M = M2
+    return {"value": ne * spec.n / dt, "unit": "particle*point evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"reference MH move, K={K}, {M} chains x {n} waste-free sweeps at beta=1e-3, "
+                      f"{ne} likelihood evaluations of N={spec.n} points, {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--particles", type=int, default=65536)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the sampler's groups are independent and this build "
+              "measures one GPU's share; use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2604_03271_amd import native, workloads
+
+    torch.cuda.init()
+    spec = workloads.config2(0)
+    P, n = args.particles, 16
+    opt = native.options(n_particles=P, n_moves=n, waste_free=True, seed=0, profile=True)
+    s = native.Sampler(spec, opt)
+    for w in range(args.warmup):
+        s.reset(1000 + w).run()
+    torch.cuda.synchronize()
+
+    prof0 = s.profile()
+    evals, lat, logz, stages = 0, [], [], []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        s.reset(k + 1)
+        s.run()
+        evals += s.evaluations()
+        lat.append(time.perf_counter() - ts)
+        logz.append(s.log_evidence())
+        stages.append(max(s.stage_info(K)[0] for K in range(1, 9)))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof1 = s.profile()
+    elapsed = t1 - t0
+    value = evals * spec.n / elapsed
+
+    # roofline of the dominant kernel (the MH move): algorithmic lane-instructions per launch
+    # over the launch's average duration from HIP events on the library's stream
+    move_evals = evals - args.steps * P * 8
+    key = (spec.peak_kind, spec.noise_kind)
+    per_unit = VALU_PER_UNIT[key] + TRANS_COST * TRANS_PER_UNIT[key]
+    launches = prof1["move_launches"] - prof0["move_launches"]
+    move_s = (prof1["move_ms"] - prof0["move_ms"]) / 1e3
+    achieved = move_evals * spec.n * per_unit / move_s
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                "kernel": "k_move", "avg_launch_ms": move_s * 1e3 / max(launches, 1),
+                "ops_per_unit": per_unit, "units_per_launch": move_evals * spec.n / max(launches, 1)}
+
+    out = {
+        "metric": "particle*point likelihood evals/s",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "XPS-like spectrum N=1001, 5 pseudo-Voigt peaks + linear background, sigma=0.02, "
+                               "K=1..8, P=65536 per K, waste-free n=16",
+                   "n_points": spec.n, "k_range": [1, 8], "particles_per_k": P, "n_moves": n,
+                   "parallelism": "single GPU, all K in one launch"},
+        "spectra_per_s": args.steps / elapsed,
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "stages_max": int(np.max(stages)),
+        "best_k": int(np.argmax(np.mean(logz, 0)) + 1),
+        "roofline": roofline,
+    }
+    if not args.no_plain:
+        sp = native.Sampler(spec, native.options(n_particles=P, n_moves=n, waste_free=True, seed=0, plain=True))
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        sp.reset(1).run()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - ts
+        out["plain_gpu"] = {"spectra_per_s": 1.0 / dt, "evals_per_s": sp.evaluations() * spec.n / dt,
+                            "note": "same kernels, one K at a time, one launch per K per stage"}
+        sp.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(spec, 5)
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -103,7 +103,8 @@ def lib():
             "or_ess": (D, [PD, I32, D, PD]),
             "or_next_delta": (D, [PD, I32, D, D, I32]),
             "or_resample": (None, [PD, I32, I32, U32, PI]),
-            "or_move": (None, [PP, I32, I32, I32, I32, D, U64, U32, U32, PD, PD, PD, PD, PD, PI]),
+            "or_move": (ctypes.c_int64, [PP, I32, I32, I32, I32, D, U64, U32, U32, PD, PD, PD, PD, PD, PI]),
+            "or_num_threads": (I32, []),
             "or_step_sizes": (None, [PD, I32, I32, PD, PD]),
             "or_update_lambda": (None, [PD, PI, I32, D]),
             "or_run": (I32, [PP, I32, ctypes.POINTER(_Options), ctypes.POINTER(_Result)]),
@@ -263,8 +264,12 @@ def update_lambda(lam, acc, proposals: float) -> np.ndarray:
     return lam
 
 
+def num_threads() -> int:
+    return lib().or_num_threads()
+
+
 def move(prob: Problem, K: int, start, startE, step, beta: float, n: int, waste_free: bool,
-         seed: int, uid: int, stage: int):
+         seed: int, uid: int, stage: int, return_evals: bool = False):
     start = np.ascontiguousarray(start, dtype=np.float64)
     startE = np.ascontiguousarray(startE, dtype=np.float64)
     step = np.ascontiguousarray(step, dtype=np.float64)
@@ -273,8 +278,11 @@ def move(prob: Problem, K: int, start, startE, step, beta: float, n: int, waste_
     out = np.zeros((P, max(d, 1)), dtype=np.float64)
     outE = np.zeros(P, dtype=np.float64)
     acc = np.zeros(max(d, 1), dtype=np.int32)
-    lib().or_move(prob.ref, K, M, n, int(bool(waste_free)), float(beta), seed, uid, stage, _pd(step),
-                  _pd(start), _pd(startE), _pd(out), _pd(outE), acc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    ne = lib().or_move(prob.ref, K, M, n, int(bool(waste_free)), float(beta), seed, uid, stage, _pd(step),
+                       _pd(start), _pd(startE), _pd(out), _pd(outE),
+                       acc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    if return_evals:
+        return out[:, :d], outE, acc[:d], int(ne)
     return out[:, :d], outE, acc[:d]
 
 

@@ -41,6 +41,10 @@
 
 #include "smc_oracle.h"
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 /* ------------------------------------------------------------------------
  * Philox4x32-10 (Salmon, Moraes, Dror & Shaw, "Parallel random numbers: as
  * easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplications with
@@ -345,7 +349,7 @@ void or_resample(const double* W, int P, int M, uint32_t r, int32_t* anc)
  * ------------------------------------------------------------------------ */
 static void mh_sweep(const or_problem* p, int K, int d, double beta, const uint32_t key[2],
                      uint32_t chain, uint32_t stage, uint32_t sweep, const double* step,
-                     double* th, double* E, int32_t* acc)
+                     double* th, double* E, int32_t* acc, int64_t* n_eval)
 {
     for (int j = 0; j < d; ++j) {
         or_prior pr = or_component_prior(p, K, j);
@@ -358,6 +362,7 @@ static void mh_sweep(const or_problem* p, int K, int d, double beta, const uint3
         double prop = old + step[j] * z;
         if (!or_prior_in_support(pr, prop)) continue;
         th[j] = prop;
+        *n_eval += 1;
         double Enew = or_energy(p, K, th);
         double log_alpha = -beta * (Enew - *E) + or_prior_logpdf(pr, prop) - or_prior_logpdf(pr, old);
         if (log(u) < log_alpha) {
@@ -370,24 +375,26 @@ static void mh_sweep(const or_problem* p, int K, int d, double beta, const uint3
 }
 
 /* Move the M start states (rows of `start`, energies `start_E`) with n sweeps at
- * inverse temperature beta.  Standard mode (waste_free = 0, M = P): particle i
+ * inverse temperature beta; returns the number of likelihood evaluations.  Standard mode (waste_free = 0, M = P): particle i
  * keeps its state after the n-th sweep.  Waste-free mode (Sec. II.B.3, M = P/n):
  * every post-sweep state of chain m is kept, in slot m*n + t.
  * acc[j] returns the accepted count of component j over all chains and sweeps. */
-void or_move(const or_problem* p, int K, int M, int n, int waste_free, double beta,
-             uint64_t seed, uint32_t uid, uint32_t stage, const double* step,
-             const double* start, const double* start_E, double* out, double* out_E, int32_t* acc)
+int64_t or_move(const or_problem* p, int K, int M, int n, int waste_free, double beta,
+                uint64_t seed, uint32_t uid, uint32_t stage, const double* step,
+                const double* start, const double* start_E, double* out, double* out_E, int32_t* acc)
 {
     int d = or_dim(p, K);
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32) ^ uid};
     int32_t* acc_chain = (int32_t*)calloc((size_t)M * (size_t)(d > 0 ? d : 1), sizeof(int32_t));
-#pragma omp parallel for schedule(dynamic, 4)
+    int64_t n_eval = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : n_eval)
     for (int m = 0; m < M; ++m) {
         double* th = (double*)malloc(sizeof(double) * (size_t)(d > 0 ? d : 1));
         memcpy(th, start + (size_t)m * d, sizeof(double) * (size_t)d);
         double E = start_E[m];
         for (int t = 0; t < n; ++t) {
-            mh_sweep(p, K, d, beta, key, (uint32_t)m, stage, (uint32_t)t, step, th, &E, acc_chain + (size_t)m * d);
+            mh_sweep(p, K, d, beta, key, (uint32_t)m, stage, (uint32_t)t, step, th, &E, acc_chain + (size_t)m * d,
+                     &n_eval);
             if (waste_free) {
                 size_t slot = (size_t)m * n + t;
                 memcpy(out + slot * d, th, sizeof(double) * (size_t)d);
@@ -406,6 +413,17 @@ void or_move(const or_problem* p, int K, int M, int n, int waste_free, double be
         acc[j] = s;
     }
     free(acc_chain);
+    return n_eval;
+}
+
+/* Threads an OpenMP region of the reference would use (1 without OpenMP). */
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* Step sizes (Sec. II.B.4, rule of the design notes): s_j = lambda_j sd_j with

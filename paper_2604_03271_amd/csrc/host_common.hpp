@@ -1,0 +1,73 @@
+// host_common.hpp -- declarations shared by the host-side translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <vector>
+
+#include "kernel_table.hpp"
+#include "smc_types.hpp"
+
+namespace smc {
+
+constexpr int kMaxK = 64;
+
+struct Tile {
+    int lc, pi, lanes, ppl;
+    bool valid;
+};
+
+struct Arena {
+    void* base;
+    size_t size;
+    size_t used;
+    void* take(size_t bytes);
+};
+
+struct PendingCopy {
+    void* dst;
+    const void* src;
+    size_t bytes;
+};
+
+// Owned copy of one problem, with FP32 images of the data.
+struct Spectrum {
+    smc_problem prob{};
+    std::vector<double> x, y;
+    std::vector<float> xf, yf;
+    std::vector<smc_prior> ppk;
+    void assign(const smc_problem& p);
+};
+
+const KernelTable& kernels();
+int params_per_peak(int peak_kind);
+int params_bg(int bg_kind);
+smc_prior component_prior(const smc_problem& p, int K, int j);
+smc_status validate(const smc_problem* p, const smc_options* o);
+double energy_constant(const smc_problem& p);
+DevPrior dev_prior(const smc_prior& p);
+Tile choose_tile(int n_points, int64_t chains, int forced_lanes);
+size_t move_lds_bytes(const Tile& t, int d);
+size_t energy_lds_bytes(const Tile& t, int d);
+void build_work(const std::vector<int>& groups, const std::vector<int>& chains_of, const Tile& t,
+                std::vector<MoveWork>& out);
+hipError_t launch_tiled(const void* fn, int n_work, size_t lds, const GroupDesc* groups, const MoveWork* work,
+                        hipStream_t s);
+size_t group_bytes(int d, int P, int M, int max_stages);
+size_t spectrum_bytes(const smc_problem& p, const smc_options& o);
+bool describe_spectrum(const Spectrum& sp, const smc_options& o, Arena& arena, GroupState* d_states_base,
+                       int first_state, std::vector<GroupDesc>& out, std::vector<PendingCopy>& copies);
+hipError_t upload_group_tables(const Spectrum& sp, const std::vector<GroupDesc>& gs, size_t first, size_t count,
+                               hipStream_t s, std::vector<std::vector<char>>& keep);
+bool device_ok();
+
+// launchers defined in stage.hip
+hipError_t launch_stage(const GroupDesc* groups, int n_groups, hipStream_t s);
+hipError_t launch_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out, int64_t n, hipStream_t s);
+hipError_t launch_bisect_hook(const float* E, int P, double beta, double rho, int iters, double* out, hipStream_t s);
+hipError_t launch_resample_hook(const double* W, int P, int M, uint32_t r, unsigned long long* cdf, int32_t* anc,
+                                hipStream_t s);
+hipError_t launch_draw(const GroupDesc* groups, int group, int64_t n_draws, hipStream_t s);
+
+}  // namespace smc

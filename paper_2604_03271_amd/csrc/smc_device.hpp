@@ -1,0 +1,201 @@
+// smc_device.hpp -- device-side building blocks of the gfx950 SMC sampler.
+//
+// Everything here runs on the GPU.  FP32 is used for the forward model
+// (Eq. forward_model with the Gaussian basis of Eq. spectral_forward_model or
+// the pseudo-Voigt basis of Eq. xps_forward_model), the energies and the
+// Metropolis decisions; FP64 only in the stage kernel (weights, ESS, evidence).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "smc_types.hpp"
+
+namespace smc {
+
+constexpr float kLn2 = 0.693147180559945309f;
+constexpr float kLog2e = 1.442695040888963407f;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds, each two
+// 32x32->64 products of counter words 0 and 2 with the published multipliers,
+// XOR of the high halves with words 1/3 and the round key, and a Weyl key
+// schedule with the published increments.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+__device__ __forceinline__ uint4 draw(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2,
+                                      uint32_t K, uint32_t purpose) {
+    return philox(make_uint4(c0, c1, c2, (K << 8) | purpose), k0, k1);
+}
+
+// (r + 1/2) / 2^32 rounded to FP32: in (0, 1].
+__device__ __forceinline__ float u01(uint32_t r) {
+    return __builtin_fmaf(static_cast<float>(r), 0x1.0p-32f, 0x1.0p-33f);
+}
+
+__device__ __forceinline__ float fast_ln(float v) { return __builtin_amdgcn_logf(v) * kLn2; }
+
+// Box-Muller, cosine branch; v_cos_f32 takes its argument in revolutions.
+__device__ __forceinline__ float box_muller(uint32_t r0, uint32_t r1) {
+    const float rad = __builtin_sqrtf(-2.0f * fast_ln(u01(r0)));
+    return rad * __builtin_amdgcn_cosf(u01(r1));
+}
+
+// Prior draw of one component (stage 0).  Uniform by inverse CDF, Normal by
+// Box-Muller, Gamma by Marsaglia & Tsang (2000), shape < 1 boosted by u^(1/a).
+__device__ inline float prior_draw(const DevPrior& pr, uint32_t k0, uint32_t k1, uint32_t K, uint32_t i,
+                                   uint32_t j) {
+    if (pr.kind == SMC_PRIOR_UNIFORM) {
+        const uint4 r = draw(k0, k1, i, 0, 256u * j, K, kPurposeInit);
+        return pr.a + (pr.b - pr.a) * u01(r.x);
+    }
+    if (pr.kind == SMC_PRIOR_NORMAL) {
+        const uint4 r = draw(k0, k1, i, 0, 256u * j, K, kPurposeInit);
+        return pr.a + pr.b * box_muller(r.x, r.y);
+    }
+    if (pr.kind == SMC_PRIOR_GAMMA) {
+        const float shape = pr.a < 1.0f ? pr.a + 1.0f : pr.a;
+        const float d = shape - 1.0f / 3.0f;
+        const float c = 1.0f / __builtin_sqrtf(9.0f * d);
+        for (uint32_t t = 0; t < 256u; ++t) {
+            const uint4 r = draw(k0, k1, i, 0, 256u * j + t, K, kPurposeInit);
+            const float z = box_muller(r.x, r.y);
+            float v = 1.0f + c * z;
+            if (v <= 0.0f) continue;
+            v = v * v * v;
+            if (fast_ln(u01(r.z)) < 0.5f * z * z + d - d * v + d * fast_ln(v)) {
+                float g = d * v;
+                if (pr.a < 1.0f) g *= __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(u01(r.w)) / pr.a);
+                return g / pr.b;
+            }
+        }
+        return pr.a / pr.b;
+    }
+    return pr.a;  // fixed
+}
+
+__device__ __forceinline__ bool prior_in_support(const DevPrior& pr, float v) {
+    if (pr.kind == SMC_PRIOR_UNIFORM) return v > pr.a && v < pr.b;
+    if (pr.kind == SMC_PRIOR_GAMMA) return v > 0.0f;
+    return __builtin_isfinite(v);
+}
+
+// ln p(new) - ln p(old) for one component inside its support.
+__device__ __forceinline__ float prior_log_ratio(const DevPrior& pr, float vn, float vo) {
+    if (pr.kind == SMC_PRIOR_GAMMA) {
+        float r = -pr.b * (vn - vo);
+        if (pr.c != 0.0f) r += pr.c * kLn2 * (__builtin_amdgcn_logf(vn) - __builtin_amdgcn_logf(vo));
+        return r;
+    }
+    if (pr.kind == SMC_PRIOR_NORMAL) {
+        const float dn = vn - pr.a, d0 = vo - pr.a;
+        return (d0 * d0 - dn * dn) * pr.c;
+    }
+    return 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// Peak profiles.  A peak's per-particle constants are hoisted out of the point
+// loop:
+//   Gaussian  A exp(-(b/2) t^2)        = A * 2^(cb t^2),        cb = -(b/2) log2 e
+//   pseudo-Voigt A[eta e^{-ln2 t^2/s^2} + (1-eta) s^2/(s^2+t^2)]
+//                                      = aG 2^(cg t^2) + aL / (s2 + t^2),
+//             cg = -1/s^2, s2 = s^2, aG = A eta, aL = A (1-eta) s^2
+//   background c0 + c1 x  (constant background: c1 = 0)
+// with t = x - mu evaluated exactly near the peak (Sterbenz).
+// ---------------------------------------------------------------------------
+struct PeakC {
+    float mu, c, s2, aG, aL;
+};
+
+template <int PK>
+__device__ __forceinline__ PeakC peak_consts(const float* th) {
+    PeakC q;
+    if constexpr (PK == SMC_PEAK_GAUSS) {
+        q.mu = th[1];
+        q.c = -0.5f * kLog2e * th[2];
+        q.s2 = 0.0f;
+        q.aG = th[0];
+        q.aL = 0.0f;
+    } else {
+        const float s = th[2];
+        q.mu = th[1];
+        q.s2 = s * s;
+        q.c = -1.0f / q.s2;
+        q.aG = th[0] * th[3];
+        q.aL = th[0] * (1.0f - th[3]) * q.s2;
+    }
+    return q;
+}
+
+__device__ __forceinline__ PeakC bg_consts(const float* th, int nbg) {
+    PeakC q{};
+    q.aG = nbg > 0 ? th[0] : 0.0f;
+    q.aL = nbg > 1 ? th[1] : 0.0f;
+    return q;
+}
+
+template <int PK>
+__device__ __forceinline__ float peak_eval(float x, const PeakC& q) {
+    const float t = x - q.mu;
+    const float t2 = t * t;
+    if constexpr (PK == SMC_PEAK_GAUSS) {
+        return q.aG * __builtin_amdgcn_exp2f(q.c * t2);
+    } else {
+        return __builtin_fmaf(q.aL, __builtin_amdgcn_rcpf(q.s2 + t2), q.aG * __builtin_amdgcn_exp2f(q.c * t2));
+    }
+}
+
+__device__ __forceinline__ float bg_eval(float x, const PeakC& q) { return __builtin_fmaf(q.aL, x, q.aG); }
+
+// Poisson deviance term f - y + y ln(y/f) = f h((y-f)/f), h(u) = (1+u) ln(1+u) - u,
+// evaluated without cancellation: with v = (y-f)/(y+f) it equals
+// (y-f) v + 2 y v (v^2/3 + v^4/5 + v^6/7 + v^8/9 + ...) for |v| < 0.1 (Loader's
+// saddle-point deviance), and the direct form otherwise.  +inf if f <= 0;
+// 0 for the padding marker y < 0.
+__device__ __forceinline__ float poisson_dev(float y, float f) {
+    const float d = y - f;
+    const float v = d * __builtin_amdgcn_rcpf(y + f);
+    const float v2 = v * v;
+    const float series = __builtin_fmaf(
+        2.0f * y * v, v2 * __builtin_fmaf(v2, __builtin_fmaf(v2, __builtin_fmaf(v2, 1.0f / 9.0f, 1.0f / 7.0f), 1.0f / 5.0f),
+                                          1.0f / 3.0f),
+        d * v);
+    const float direct = y > 0.0f ? __builtin_fmaf(y, fast_ln(y * __builtin_amdgcn_rcpf(f)), -d) : f;
+    const float r = __builtin_fabsf(v) < 0.1f ? series : direct;
+    return y < 0.0f ? 0.0f : (f > 0.0f ? r : __builtin_inff());
+}
+
+// ---------------------------------------------------------------------------
+// Sum over the L consecutive lanes of a chain inside one wavefront.  Every step
+// is a butterfly whose two operands are swapped between partner lanes, so all
+// L lanes end with the same bits (IEEE addition is commutative).
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp_swap(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+
+template <int L>
+__device__ __forceinline__ float group_sum(float v) {
+    v += dpp_swap<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_swap<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_swap<0x141>(v);  // row_half_mirror: quads of a half-row
+    v += dpp_swap<0x140>(v);  // row_mirror: halves of a 16-lane row
+    if constexpr (L >= 32) v += __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), 0x401F));  // xor 16
+    if constexpr (L >= 64) v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+}  // namespace smc

@@ -1,0 +1,70 @@
+// smc_types.hpp -- data layout shared by the host driver and the kernels.
+//
+// One "group" is the SMC sampler of one (spectrum, K) pair: its particles,
+// adaptation state and tempering state live in device memory and are described
+// by a GroupDesc.  All kernels index groups through a device array of
+// descriptors, so one launch can serve any mix of spectra and peak counts.
+#pragma once
+
+#include <stdint.h>
+
+#include "smc.h"
+
+namespace smc {
+
+enum { kPurposeInit = 1, kPurposeResample = 2, kPurposeMove = 3 };
+
+// Prior of one component in FP32 with the constant its log-density ratio needs:
+// gamma: c = shape - 1 (a = shape, b = rate); normal: c = 1 / (2 sd^2) (a = mean, b = sd);
+// uniform: a = lo, b = hi; fixed: a = value.
+struct DevPrior {
+    int32_t kind;
+    float a, b, c;
+};
+
+// Tempering state of a group (device resident).
+struct GroupState {
+    double beta;      // inverse temperature of the particles' current target
+    double logz;      // running log Z without the likelihood's constant
+    double delta, ess, lse;
+    int32_t stage;    // stages completed (0 = prior draws only)
+    int32_t done;     // 1 once the final move at beta = 1 has run
+    int32_t status;   // SMC_OK or SMC_ENUMERIC
+    int32_t pad;
+    unsigned long long evals;  // likelihood evaluations of Metropolis proposals
+};
+
+constexpr int kTraceCols = 6;  // beta, delta, ess, lse, logz, acceptance
+
+struct GroupDesc {
+    // model
+    int32_t n, K, d, np, nbg, peak_kind, bg_kind, noise_kind;
+    float inv2s2;               // 1 / (2 sigma^2) for Gaussian noise
+    int32_t pad0;
+    const float* x;             // [n]
+    const float* y;             // [n]
+    const DevPrior* prior;      // [d]
+    // particles
+    int32_t P, M, n_moves, waste_free;
+    float* theta;               // [d][P]
+    float* energy;              // [P]
+    float* start;               // [d][M] resampled start states of the move
+    float* start_e;             // [M]
+    unsigned long long* cdf;    // [P] integer CDF scratch
+    double* lambda;             // [d] step-size multipliers
+    float* step;                // [d] random-walk scales of the current stage
+    uint32_t* acc;              // [d] accepted proposals of the last move
+    GroupState* st;
+    double* trace;              // [max_stages][kTraceCols]
+    double rho;
+    int32_t bisect_iters, max_stages;
+    uint32_t key0, key1;
+    int32_t kidx, pad1;
+};
+
+// One workgroup of the move / energy kernels: chains [chain0, chain0 + nchains) of a group.
+struct MoveWork {
+    int32_t group, chain0, nchains, pad;
+};
+
+}  // namespace smc
