@@ -15,8 +15,7 @@
 //   D = model without the current term          (Poisson counts)
 // and G = the current term's value.  A proposal then costs one profile
 // evaluation per point; moving to the next term costs one more.  D and G are
-// rebuilt from scratch at the start of every sweep, so rounding cannot
-// accumulate beyond one sweep.
+// rebuilt from scratch every few sweeps, so rounding cannot accumulate.
 #pragma once
 
 #include "smc_device.hpp"
@@ -33,10 +32,16 @@ __device__ __forceinline__ float point_term(float D, float g, float y) {
     }
 }
 
-// Points beyond N are loaded with x = kFarX, where every peak profile underflows
-// to 0 and the background is masked, and with y = 0 (Gaussian noise) or y = -1
-// (Poisson, which the deviance term maps to 0): they contribute exactly 0.
+// Points beyond N (the tile holds LC * PPL >= N) are loaded with x = kFarX,
+// where every peak profile underflows to 0 and the background is masked, and
+// with y = 0 (Gaussian noise) or y = -1 (Poisson, which the deviance term maps
+// to 0): they contribute exactly 0, so the point loops need no bounds.
 constexpr float kFarX = 1.0e18f;
+
+// The residual cache D, G is rebuilt from the parameters every kRebuildEvery
+// sweeps (and at every chain start), which bounds the rounding it accumulates
+// through term-to-term updates to a few sweeps.
+constexpr int kRebuildEvery = 4;
 
 template <int PK, int NZ, int L, int WPC, int PPL>
 struct ChainState {
@@ -46,10 +51,8 @@ struct ChainState {
     float D[PPL];
     float G[PPL];
     float Gn[PPL];
-    int rows;  // rows of points actually present (uniform across the chain), <= PPL
 
     __device__ __forceinline__ void load_points(const GroupDesc& g, int lane) {
-        rows = min(PPL, (g.n + LC - 1) / LC);
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
             const int i = lane + p * LC;
@@ -67,18 +70,10 @@ struct ChainState {
     __device__ __forceinline__ void eval_term(bool is_bg, const PeakC& q, float* out) const {
         if (is_bg) {
 #pragma unroll
-            for (int p = 0; p < PPL; ++p) {
-                if (p < rows) {
-                    out[p] = x[p] < 1.0e17f ? bg_eval(x[p], q) : 0.0f;
-                }
-            }
+            for (int p = 0; p < PPL; ++p) out[p] = x[p] < 1.0e17f ? bg_eval(x[p], q) : 0.0f;
         } else {
 #pragma unroll
-            for (int p = 0; p < PPL; ++p) {
-                if (p < rows) {
-                    out[p] = peak_eval<PK>(x[p], q);
-                }
-            }
+            for (int p = 0; p < PPL; ++p) out[p] = peak_eval<PK>(x[p], q);
         }
     }
 
@@ -86,11 +81,7 @@ struct ChainState {
     __device__ __forceinline__ float partial(const float* gv) const {
         float acc = 0.0f;
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-            if (p < rows) {
-                acc += point_term<NZ>(D[p], gv[p], NZ == SMC_NOISE_POISSON ? y[p] : 0.0f);
-            }
-        }
+        for (int p = 0; p < PPL; ++p) acc += point_term<NZ>(D[p], gv[p], NZ == SMC_NOISE_POISSON ? y[p] : 0.0f);
         return acc;
     }
 
@@ -100,24 +91,19 @@ struct ChainState {
         if constexpr (NZ == SMC_NOISE_GAUSS) {
 #pragma unroll
             for (int p = 0; p < PPL; ++p) {
-                if (p < rows) {
-                    const int i = lane + p * LC;
-                    D[p] = i < g.n ? g.y[i] : 0.0f;
-                }
+                const int i = lane + p * LC;
+                D[p] = i < g.n ? g.y[i] : 0.0f;
             }
         } else {
 #pragma unroll
             for (int p = 0; p < PPL; ++p) D[p] = 0.0f;
         }
         for (int k = kt - 1; k >= 1; --k) {
-            const PeakC q = term_consts(g, th, k);
-            eval_term(k == g.K, q, Gn);
+            eval_term(k == g.K, term_consts(g, th, k), Gn);
 #pragma unroll
             for (int p = 0; p < PPL; ++p) {
-                if (p < rows) {
-                    if constexpr (NZ == SMC_NOISE_GAUSS) D[p] -= Gn[p];
-                    else D[p] += Gn[p];
-                }
+                if constexpr (NZ == SMC_NOISE_GAUSS) D[p] -= Gn[p];
+                else D[p] += Gn[p];
             }
         }
         eval_term(0 == g.K, term_consts(g, th, 0), G);
@@ -129,21 +115,15 @@ struct ChainState {
         eval_term(is_bg, q, Gn);
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
-            if (p < rows) {
-                if constexpr (NZ == SMC_NOISE_GAUSS) D[p] = (D[p] - G[p]) + Gn[p];
-                else D[p] = (D[p] + G[p]) - Gn[p];
-                G[p] = Gn[p];
-            }
+            if constexpr (NZ == SMC_NOISE_GAUSS) D[p] = (D[p] - G[p]) + Gn[p];
+            else D[p] = (D[p] + G[p]) - Gn[p];
+            G[p] = Gn[p];
         }
     }
 
     __device__ __forceinline__ void accept() {
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-            if (p < rows) {
-                G[p] = Gn[p];
-            }
-        }
+        for (int p = 0; p < PPL; ++p) G[p] = Gn[p];
     }
 };
 
@@ -205,8 +185,17 @@ __global__ void __launch_bounds__(256) k_energy(const GroupDesc* __restrict__ gr
 // LDS per chain slot: theta[d], increment s_j z_j [d], ln u_j [d]; then the
 // per-component accept counters [d] and the cross-wave reduction buffer.
 // ---------------------------------------------------------------------------
+// Waves per SIMD the register allocator is asked to leave room for: the cached
+// point state grows with PPL (x, D, G, Gn per point, and y for Poisson counts);
+// these limits are the largest that compile without spilling on gfx950.
+template <int NZ, int PPL>
+constexpr int move_min_waves() {
+    if constexpr (NZ == SMC_NOISE_GAUSS) return PPL <= 12 ? 5 : (PPL <= 16 ? 4 : (PPL <= 20 ? 3 : 2));
+    else return PPL <= 8 ? 5 : (PPL <= 12 ? 4 : (PPL <= 16 ? 3 : 2));
+}
+
 template <int PK, int NZ, int L, int WPC, int PPL>
-__global__ void __launch_bounds__(256) k_move(const GroupDesc* __restrict__ groups,
+__global__ void __launch_bounds__(256, move_min_waves<NZ, PPL>()) k_move(const GroupDesc* __restrict__ groups,
                                               const MoveWork* __restrict__ work) {
     using CS = ChainState<PK, NZ, L, WPC, PPL>;
     constexpr int LC = CS::LC;
@@ -258,8 +247,12 @@ __global__ void __launch_bounds__(256) k_move(const GroupDesc* __restrict__ grou
         }
         __syncthreads();
         if (active) {
-            E = chain_sum<L, WPC>(cs.rebuild(g, th, lane), red, parity);
-            if (NZ == SMC_NOISE_GAUSS) E *= g.inv2s2;
+            if (t % kRebuildEvery == 0) {
+                E = chain_sum<L, WPC>(cs.rebuild(g, th, lane), red, parity);
+                if (NZ == SMC_NOISE_GAUSS) E *= g.inv2s2;
+            } else if (kt > 1) {
+                cs.advance(0 == g.K, CS::term_consts(g, th, 0));
+            }
             for (int k = 0; k < kt; ++k) {
                 const bool is_bg = k == g.K;
                 const int j0 = is_bg ? g.K * g.np : k * g.np;

@@ -69,5 +69,6 @@ hipError_t launch_bisect_hook(const float* E, int P, double beta, double rho, in
 hipError_t launch_resample_hook(const double* W, int P, int M, uint32_t r, unsigned long long* cdf, int32_t* anc,
                                 hipStream_t s);
 hipError_t launch_draw(const GroupDesc* groups, int group, int64_t n_draws, hipStream_t s);
+hipError_t launch_draw_items(const GroupDesc* groups, const MoveWork* items, int n_items, hipStream_t s);
 
 }  // namespace smc

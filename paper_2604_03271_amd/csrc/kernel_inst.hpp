@@ -14,13 +14,15 @@ inline void reg_one(KernelTable& t, int lc, int pi) {
     t.energy[PK][NZ][lc][pi] = reinterpret_cast<const void*>(&k_energy<PK, NZ, L, WPC, PPL>);
 }
 
+template <int PK, int NZ, int L, int WPC, int... PPLS>
+inline void reg_list(KernelTable& t, int lc) {
+    int pi = 0;
+    (reg_one<PK, NZ, L, WPC, PPLS>(t, lc, pi++), ...);
+}
+
 template <int PK, int NZ, int L, int WPC>
 inline void reg_ppl(KernelTable& t, int lc) {
-    reg_one<PK, NZ, L, WPC, 2>(t, lc, 0);
-    reg_one<PK, NZ, L, WPC, 4>(t, lc, 1);
-    reg_one<PK, NZ, L, WPC, 8>(t, lc, 2);
-    reg_one<PK, NZ, L, WPC, 16>(t, lc, 3);
-    reg_one<PK, NZ, L, WPC, 32>(t, lc, 4);
+    reg_list<PK, NZ, L, WPC, 1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32>(t, lc);
 }
 
 template <int PK, int NZ>

@@ -1,8 +1,8 @@
 // kernel_table.hpp -- host-side table of the move / energy kernel instantiations.
 //
 // Tiles: lanes per chain (16, 32 or 64 lanes of one wavefront, or 4 whole
-// wavefronts = 256 lanes) x points per lane (PPL, a compile-time register
-// budget; the row loops stop at ceil(N / lanes)).
+// wavefronts = 256 lanes) x points per lane (PPL, compile time; the smallest
+// listed value >= ceil(N / lanes), points beyond N padded with zero-weight ones).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,8 +11,8 @@ namespace smc {
 
 constexpr int kNumLaneCfg = 4;            // 16x1, 32x1, 64x1, 64x4
 constexpr int kLanesOf[kNumLaneCfg] = {16, 32, 64, 256};
-constexpr int kNumPpl = 5;
-constexpr int kPplOf[kNumPpl] = {2, 4, 8, 16, 32};
+constexpr int kNumPpl = 16;
+constexpr int kPplOf[kNumPpl] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32};
 
 struct KernelTable {
     const void* move[2][2][kNumLaneCfg][kNumPpl];

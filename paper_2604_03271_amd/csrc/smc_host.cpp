@@ -594,7 +594,7 @@ static smc_status step_plain(smc_ctx* c, int32_t* all_done) {
         if (st != SMC_OK) return st;
         if (c->states[gi].status != SMC_OK) return c->states[gi].status;
         if (c->states[gi].beta >= 1.0) {
-            if (launch_stage(c->d_groups + gi, 1, c->stream) != hipSuccess) return SMC_EDEVICE;
+            if (timed_stage(c, c->d_groups + gi, 1) != hipSuccess) return SMC_EDEVICE;
             st = read_states(c);
             if (st != SMC_OK) return st;
         }
@@ -624,7 +624,7 @@ extern "C" smc_status smc_step(smc_ctx* c, int32_t* all_done) {
     }
     if (done) {
         // one more stage launch records the final acceptance and marks the groups done
-        if (launch_stage(c->d_groups, c->ng, c->stream) != hipSuccess) return SMC_EDEVICE;
+        if (timed_stage(c, c->d_groups, c->ng) != hipSuccess) return SMC_EDEVICE;
         st = read_states(c);
         if (st != SMC_OK) return st;
         c->finished = true;

@@ -20,111 +20,167 @@ constexpr int kStageThreads = 1024;
 constexpr int kStageWaves = kStageThreads / 64;
 
 struct StageShared {
-    double red[2][kStageWaves];
+    double red[4][kStageWaves];
     unsigned long long scan[kStageWaves];
     unsigned long long total;
 };
 
-// Sum of two FP64 values over the workgroup; every thread receives the same bits.
-__device__ inline double2 block_sum2(double a, double b, StageShared& sh) {
+// Sums of up to four FP64 values over the workgroup; every thread receives the same bits.
+template <int NV>
+__device__ inline void block_sum(double* v, StageShared& sh) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        a += __shfl_xor(a, o, 64);
-        b += __shfl_xor(b, o, 64);
-    }
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) v[q] += __shfl_xor(v[q], o, 64);
     const int w = threadIdx.x >> 6;
     __syncthreads();
-    if ((threadIdx.x & 63) == 0) {
-        sh.red[0][w] = a;
-        sh.red[1][w] = b;
-    }
-    __syncthreads();
-    double s = 0.0, t = 0.0;
-    for (int q = 0; q < kStageWaves; ++q) {
-        s += sh.red[0][q];
-        t += sh.red[1][q];
-    }
-    return make_double2(s, t);
-}
-
-__device__ inline double block_min(double v, int& any_nan, StageShared& sh) {
-    int nan_flag = any_nan;
+    if ((threadIdx.x & 63) == 0)
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        v = fmin(v, __shfl_xor(v, o, 64));
-        nan_flag |= __shfl_xor(nan_flag, o, 64);
-    }
-    const int w = threadIdx.x >> 6;
+        for (int q = 0; q < NV; ++q) sh.red[q][w] = v[q];
     __syncthreads();
-    if ((threadIdx.x & 63) == 0) {
-        sh.red[0][w] = v;
-        sh.red[1][w] = nan_flag;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double s = 0.0;
+        for (int k = 0; k < kStageWaves; ++k) s += sh.red[q][k];
+        v[q] = s;
     }
-    __syncthreads();
-    double m = sh.red[0][0];
-    int nf = 0;
-    for (int q = 0; q < kStageWaves; ++q) {
-        m = fmin(m, sh.red[0][q]);
-        nf |= sh.red[1][q] != 0.0;
-    }
-    any_nan = nf;
-    return m;
 }
 
-// S1 = sum exp(-delta a_i), S2 = sum exp(-delta a_i)^2 with a_i = E_i - min E.
-__device__ inline double2 weight_sums(const float* E, int P, double emin, double delta, StageShared& sh) {
-    double s1 = 0.0, s2 = 0.0;
+// Weight sums at increment delta, with a_i = E_i - min E and w_i = exp(-delta a_i):
+// s[0] = sum w, s[1] = sum w^2, and with NV = 4 also s[2] = sum a w, s[3] = sum a w^2.
+template <int NV>
+__device__ inline void weight_sums(const float* E, int P, double emin, double delta, double* s, StageShared& sh) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) s[q] = 0.0;
     for (int i = threadIdx.x; i < P; i += kStageThreads) {
-        const double w = exp(-delta * (static_cast<double>(E[i]) - emin));
-        s1 += w;
-        s2 += w * w;
+        const double a = static_cast<double>(E[i]) - emin;
+        const double w = exp(-delta * a);
+        s[0] += w;
+        s[1] += w * w;
+        if constexpr (NV == 4) {
+            const double aw = w > 0.0 ? a * w : 0.0;
+            s[2] += aw;
+            s[3] += aw * w;
+        }
     }
-    return block_sum2(s1, s2, sh);
+    block_sum<NV>(s, sh);
 }
 
 struct BisectOut {
-    double delta, ess, lse, emin;
+    double delta, ess, lse, emin, s1;
     int ok;
 };
 
-// Next increment: all of 1 - beta if ESS there >= rho P, else `iters` halvings of
-// [0, 1 - beta] keeping the low end; the high end if no tested point qualified.
+// The next increment, defined as the result of `iters` halvings of [0, 1 - beta]
+// that keep the low end where ESS >= rho P (all of 1 - beta if ESS there already
+// qualifies; the final high end if no tested point qualified).
+//
+// The halvings are replayed, not evaluated one by one.  g(delta) = ln ESS(delta) -
+// ln(rho P) is non-increasing (the weights exp(-delta a) concentrate as delta
+// grows), so Newton's method on g, kept inside a bracket [L, U] with g(L) >= 0 >
+// g(U) and started from the small-delta expansion ESS/P ~ 1/(1 + delta^2 Var E),
+// converges to the root r in a few passes (g' = 2 (sum a w^2 / sum w^2 - sum a w /
+// sum w) comes from the same pass).  Each halving then keeps the low end iff its
+// midpoint is <= r.  This reproduces the halvings except where the FP64 rounding
+// of the weight sums decides ESS(mid) >= rho P, which is equally true of any
+// implementation of them.  Without convergence (not seen) the midpoints are
+// evaluated one by one.
 __device__ inline BisectOut bisect(const float* E, int P, double beta, double rho, int iters, StageShared& sh) {
     BisectOut o;
-    int nan = 0;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};  // NaN flag, finite count, sum E, sum E^2 (finite E)
     double emin = __builtin_inf();
     for (int i = threadIdx.x; i < P; i += kStageThreads) {
         const float e = E[i];
-        nan |= __builtin_isnan(e);
+        if (__builtin_isnan(e)) v[0] = 1.0;
+        if (__builtin_isfinite(e)) {
+            const double x = static_cast<double>(e);
+            v[1] += 1.0;
+            v[2] += x;
+            v[3] += x * x;
+        }
         emin = fmin(emin, static_cast<double>(e));
     }
-    emin = block_min(emin, nan, sh);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) emin = fmin(emin, __shfl_xor(emin, off, 64));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh.red[3][threadIdx.x >> 6] = emin;  // read before block_sum reuses red
+    __syncthreads();
+    {
+        double m = sh.red[3][0];
+        for (int k = 1; k < kStageWaves; ++k) m = fmin(m, sh.red[3][k]);
+        emin = m;
+    }
+    block_sum<4>(v, sh);
+    const bool nan = v[0] != 0.0;
+    const double nfin = v[1];
     o.emin = emin;
     o.ok = !nan && emin < __builtin_inf();
     if (!o.ok) {
-        o.delta = o.ess = o.lse = 0.0;
+        o.delta = o.ess = o.lse = o.s1 = 0.0;
         return o;
     }
     const double target = rho * static_cast<double>(P);
-    double hi = 1.0 - beta;
-    double2 s = weight_sums(E, P, emin, hi, sh);
+    const double H = 1.0 - beta;
+    double s[4];
+    weight_sums<2>(E, P, emin, H, s, sh);
     double delta;
-    if (s.x * s.x / s.y >= target) {
+    if (s[0] * s[0] / s[1] >= target) {
+        delta = H;
+    } else if (nfin < target) {
+        // ESS(delta) <= number of finite energies < rho P for every delta > 0: every halving
+        // keeps the high end, which ends at H / 2^iters (exact in FP64)
+        double hi = H;
+        for (int it = 0; it < iters; ++it) hi = 0.5 * (0.0 + hi);
         delta = hi;
+        weight_sums<2>(E, P, emin, delta, s, sh);
     } else {
-        double lo = 0.0;
+        const double lt = log(target);
+        const double mean = v[2] / nfin;
+        const double var = fmax(v[3] / nfin - mean * mean, 0.0);
+        double L = 0.0, U = H;
+        double x = var > 0.0 ? sqrt((1.0 / rho - 1.0) / var) : 0.5 * H;
+        if (!(x > L && x < U)) x = 0.5 * H;
+        double r = -1.0;
+        for (int it = 0; it < 40; ++it) {
+            weight_sums<4>(E, P, emin, x, s, sh);
+            const double g = 2.0 * log(s[0]) - log(s[1]) - lt;
+            const double gp = 2.0 * (s[3] / s[1] - s[2] / s[0]);
+            if (g >= 0.0) L = x;
+            else U = x;
+            const bool newton = gp < 0.0;
+            const double step = newton ? -g / gp : 0.0;
+            if (newton && fabs(step) <= 4e-16 * x) {
+                r = fmin(fmax(x + step, L), U);
+                break;
+            }
+            if (U - L <= 1e-15 * U) {
+                r = 0.5 * (L + U);
+                break;
+            }
+            double xn = x + step;
+            if (!newton || !(xn > L && xn < U)) xn = L > 0.0 ? sqrt(L * U) : 0.125 * U;
+            x = xn;
+        }
+        double lo = 0.0, hi = H;
         for (int it = 0; it < iters; ++it) {
             const double mid = 0.5 * (lo + hi);
-            const double2 t = weight_sums(E, P, emin, mid, sh);
-            if (t.x * t.x / t.y >= target) lo = mid;
+            bool keep_low;
+            if (r >= 0.0) {
+                keep_low = mid <= r;
+            } else {
+                weight_sums<2>(E, P, emin, mid, s, sh);
+                keep_low = s[0] * s[0] / s[1] >= target;
+            }
+            if (keep_low) lo = mid;
             else hi = mid;
         }
         delta = lo > 0.0 ? lo : hi;
-        s = weight_sums(E, P, emin, delta, sh);
+        weight_sums<2>(E, P, emin, delta, s, sh);
     }
     o.delta = delta;
-    o.ess = s.x * s.x / s.y;
-    o.lse = -delta * emin + log(s.x);
+    o.ess = s[0] * s[0] / s[1];
+    o.lse = -delta * emin + log(s[0]);
+    o.s1 = s[0];
     return o;
 }
 
@@ -208,7 +264,7 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(const GroupDesc* __rest
     const int stage_prev = st->stage;
 
     // 1. lambda_j <- clamp(lambda_j exp(acc_j - 0.44), 0.01, 10) after a move
-    if (stage_prev > 0) {
+    if (stage_prev > 0 && threadIdx.x == 0) {
         const double props = static_cast<double>(M) * g.n_moves;
         double acc_sum = 0.0;
         int nfree = 0;
@@ -217,10 +273,9 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(const GroupDesc* __rest
             const double a = g.acc[j] / props;
             acc_sum += a;
             ++nfree;
-            if (threadIdx.x == 0) g.lambda[j] = fmin(10.0, fmax(0.01, g.lambda[j] * exp(a - 0.44)));
+            g.lambda[j] = fmin(10.0, fmax(0.01, g.lambda[j] * exp(a - 0.44)));
         }
-        if (threadIdx.x == 0 && stage_prev <= g.max_stages)
-            g.trace[(stage_prev - 1) * kTraceCols + 5] = nfree ? acc_sum / nfree : 0.0;
+        if (stage_prev <= g.max_stages) g.trace[(stage_prev - 1) * kTraceCols + 5] = nfree ? acc_sum / nfree : 0.0;
     }
     __syncthreads();
     for (int j = threadIdx.x; j < d; j += kStageThreads) g.acc[j] = 0u;
@@ -248,9 +303,7 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(const GroupDesc* __rest
     }
     double beta_new = (b.delta == 1.0 - beta) ? 1.0 : beta + b.delta;
     if (beta_new > 1.0) beta_new = 1.0;
-    const double2 s = weight_sums(g.energy, P, b.emin, b.delta, sh);
-    const double s1 = s.x;
-    const double emin = b.emin, delta = b.delta;
+    const double s1 = b.s1, emin = b.emin, delta = b.delta;
 
     // 4. resampling
     const float* E = g.energy;
@@ -345,7 +398,26 @@ __global__ void k_draw(const GroupDesc* __restrict__ groups, int group) {
                                               static_cast<uint32_t>(i), static_cast<uint32_t>(j));
 }
 
+// Stage-0 draws of many groups: each work item is a run of <= 256 consecutive draws
+// (linear index j * P + i) of one group.
+__global__ void k_draw_items(const GroupDesc* __restrict__ groups, const MoveWork* __restrict__ items) {
+    const MoveWork w = items[blockIdx.x];
+    if (static_cast<int>(threadIdx.x) >= w.nchains) return;
+    const GroupDesc& g = groups[w.group];
+    const int64_t t = static_cast<int64_t>(w.chain0) + threadIdx.x;
+    const int j = static_cast<int>(t / g.P), i = static_cast<int>(t % g.P);
+    g.theta[(size_t)j * g.P + i] = prior_draw(g.prior[j], g.key0, g.key1, static_cast<uint32_t>(g.K),
+                                              static_cast<uint32_t>(i), static_cast<uint32_t>(j));
+}
+
 // ------------------------------------------------------------------ launchers
+
+hipError_t launch_draw_items(const GroupDesc* groups, const MoveWork* items, int n_items, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_draw_items, dim3(static_cast<unsigned>(n_items)), dim3(256), 0, s, groups, items);
+    return hipGetLastError();
+}
+
 
 hipError_t launch_stage(const GroupDesc* groups, int n_groups, hipStream_t s) {
     hipLaunchKernelGGL(k_stage, dim3(n_groups), dim3(kStageThreads), 0, s, groups);

@@ -35,3 +35,14 @@ def energy_constant(spec) -> float:
 
 def f32(a):
     return np.asarray(a, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def delta_ok(orc, E, beta, d_gpu, d_ref, rho=0.5):
+    """The GPU increment equals the reference's halving result, or (where the FP64 rounding
+    of the weight sums decides the last halvings) is itself a root of ESS = rho P to FP64
+    precision."""
+    width = (1.0 - beta) * 2.0 ** -50
+    if abs(d_gpu - d_ref) <= 4 * width + 1e-12 * d_ref:
+        return True
+    target = rho * len(E)
+    return abs(orc.ess(E, d_gpu)[0] / target - 1.0) <= 1e-12

@@ -1,0 +1,117 @@
+"""GPU tests of the batched path (many spectra, every K, one captured stage replayed) and
+the served path (continuous batching): each spectrum's result is bit-identical alone,
+in a batch and in the server's mix, because its tile depends on its own shape and its
+random streams on its own seed and uid (Sec. II.B.2 sampler per (spectrum, K))."""
+import time
+
+import numpy as np
+import pytest
+
+from gpu_util import say, torch_cuda
+from paper_2604_03271_amd import native, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_batch(n=6, P=1024):
+    specs = W.config4(n_spectra=n, index0=100)
+    for sp in specs:
+        sp.k_max = 3
+    return specs, dict(n_particles=P, n_moves=16, waste_free=True, seed=21)
+
+
+def _alone(spec, kw):
+    s = native.Sampler(spec, native.options(**kw))
+    s.run()
+    out = s.log_evidence()
+    s.close()
+    return out
+
+
+def test_batch_equals_alone():
+    torch_cuda()
+    specs, kw = _small_batch()
+    say("batch", [sp.n for sp in specs])
+    got = native.smc_batch_run(specs, native.options(**kw))
+    for sp, lz in zip(specs, got):
+        ref = _alone(sp, kw)
+        assert lz.shape == ref.shape
+        assert np.array_equal(lz, ref), (lz, ref)
+        assert np.all(np.isfinite(lz))
+
+
+def test_batch_reference_statistics(orc):
+    """One batched spectrum against the FP64 reference: same argmax K and close log Z."""
+    torch_cuda()
+    specs, kw = _small_batch(n=3, P=2048)
+    say("batch vs reference")
+    got = native.smc_batch_run(specs, native.options(**kw))
+    sp = specs[1]
+    opr = orc.Problem(sp)
+    ref = [orc.run(opr, K, 2048, 16, True, 5, sp.uid).log_evidence for K in range(1, 4)]
+    assert int(np.argmax(got[1])) == int(np.argmax(ref))
+    assert np.max(np.abs(np.asarray(got[1]) - np.asarray(ref))) < 1.0
+
+
+def _server_results(server, n, timeout=120.0):
+    out = {}
+    res = (native.smc_result * 64)()
+    t0 = time.time()
+    while len(out) < n and time.time() - t0 < timeout:
+        k = native.c_i32()
+        st = native.lib().smc_server_poll(server, res, 64, native.ctypes.byref(k), 200)
+        assert st in (native.SMC_OK, native.SMC_EAGAIN), native.strerror(st)
+        for i in range(k.value):
+            out[int(res[i].request_id)] = (res[i].status, list(res[i].logz[:res[i].k_max - res[i].k_min + 1]),
+                                           res[i].best_k, res[i].latency_s)
+    return out
+
+
+def _server(budget, kw):
+    srv = native.c_vp()
+    st = native.lib().smc_server_create(native.ctypes.byref(srv), budget, native.ctypes.byref(native.options(**kw)))
+    assert st == 0, native.strerror(st)
+    return srv
+
+
+def test_server_equals_alone():
+    torch_cuda()
+    specs, kw = _small_batch(n=5)
+    say("server mix")
+    srv = _server(1 << 30, kw)
+    probs = [native.Problem(sp) for sp in specs]
+    try:
+        for i, pr in enumerate(probs):
+            assert native.lib().smc_server_submit(srv, pr.ref, 100 + i) == 0
+            time.sleep(0.01 * i)   # arrivals spread over time: later ones join a running pool
+        res = _server_results(srv, len(specs))
+    finally:
+        native.lib().smc_server_destroy(srv)
+    assert len(res) == len(specs)
+    for i, sp in enumerate(specs):
+        st, lz, best, lat = res[100 + i]
+        assert st == 0 and lat > 0
+        ref = _alone(sp, kw)
+        assert np.array_equal(np.asarray(lz), ref), (lz, ref)
+        assert best == int(np.argmax(ref)) + sp.k_min
+
+
+def test_server_admission_under_small_budget():
+    torch_cuda()
+    specs, kw = _small_batch(n=4)
+    probs = [native.Problem(sp) for sp in specs]
+    need = max(native.lib().smc_server_request_bytes(pr.ref, native.ctypes.byref(native.options(**kw))) for pr in probs)
+    assert need > 0
+    say("server budget", need)
+    srv = _server(int(need * 1.5), kw)   # one request at a time fits
+    try:
+        for i, pr in enumerate(probs):
+            assert native.lib().smc_server_submit(srv, pr.ref, i) == 0
+        big = native.Problem(W.config2(0))
+        assert native.lib().smc_server_submit(srv, big.ref, 99) == native.SMC_EBUDGET
+        res = _server_results(srv, len(probs))
+    finally:
+        native.lib().smc_server_destroy(srv)
+    assert sorted(res) == list(range(len(probs)))
+    for i, sp in enumerate(specs):
+        assert np.array_equal(np.asarray(res[i][1]), _alone(sp, kw))

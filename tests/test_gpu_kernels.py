@@ -12,7 +12,7 @@ import math
 import numpy as np
 import pytest
 
-from gpu_util import dev, energy_constant, f32, say, torch_cuda
+from gpu_util import delta_ok, dev, energy_constant, f32, say, torch_cuda
 from paper_2604_03271_amd import native, workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -145,11 +145,20 @@ def test_energy_every_tile_same_values(orc):
 # ------------------------------------------------------------------ bisection / weights
 
 def _fp32_energies(rng, P, scale):
+    if scale == -1.0:   # heavy tail with some infinite energies
+        E = rng.gamma(0.3, 1000.0, P)
+        E[rng.integers(0, P, P // 10)] = np.inf
+        return f32(E)
+    if scale == -2.0:   # one particle far below the rest
+        E = np.full(P, 50.0)
+        E[3] = 0.0
+        return E
     return f32(rng.gamma(2.0, scale, P) + 100.0)
 
 
 @pytest.mark.parametrize("P,scale,beta", [(4, 1.0, 0.0), (512, 1.0, 0.0), (4096, 50.0, 0.3),
-                                         (65536, 5.0, 0.0), (1000, 1e-4, 0.9), (777, 1e3, 0.999)])
+                                         (65536, 5.0, 0.0), (1000, 1e-4, 0.9), (777, 1e3, 0.999),
+                                         (20000, 3e4, 0.0), (4096, -1.0, 0.2), (17, -2.0, 0.0)])
 def test_bisection_matches_reference(orc, P, scale, beta):
     torch = torch_cuda()
     rng = np.random.default_rng(P)
@@ -158,12 +167,11 @@ def test_bisection_matches_reference(orc, P, scale, beta):
     got = native.smc_kernel_ess_bisect(dev(E, torch.float32), beta, 0.5, 50)
     d_ref = orc.next_delta(E, beta, 0.5, 50)
     ess_ref, lse_ref = orc.ess(E, d_ref)
-    width = (1 - beta) * 2.0 ** -50
-    assert abs(got["delta"] - d_ref) <= 4 * width + 1e-12 * d_ref
+    assert delta_ok(orc, E, beta, got["delta"], d_ref), (got["delta"], d_ref)
     assert got["ess"] == pytest.approx(orc.ess(E, got["delta"])[0], rel=1e-11)
     assert got["lse"] == pytest.approx(orc.ess(E, got["delta"])[1], rel=1e-12, abs=1e-9)
     assert got["emin"] == E.min()
-    assert got["ess"] >= 0.5 * P * (1 - 1e-12)
+    assert got["ess"] >= 0.5 * P * (1 - 1e-12) or np.isfinite(E).sum() < 0.5 * P
 
 
 def test_bisection_closed_form_four_particles():

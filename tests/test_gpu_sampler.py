@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 from scipy import stats
 
-from gpu_util import dev, energy_constant, f32, say, torch_cuda
+from gpu_util import delta_ok, dev, energy_constant, f32, say, torch_cuda
 from paper_2604_03271_amd import native, workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -208,3 +208,26 @@ def test_plain_path_same_results():
     a = _gpu_logz(spec, 4, n_particles=1024, n_moves=10, waste_free=False)
     b = _gpu_logz(spec, 4, n_particles=1024, n_moves=10, waste_free=False, plain=True)
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("cfg,P,wf,n", [("config2", 65536, True, 16), ("config3", 16384, True, 16),
+                                        ("config1", 512, False, 10)])
+def test_stage_matches_reference_at_full_size(orc, cfg, P, wf, n):
+    """The stage kernel (spread over several workgroups per K at these sizes) against the
+    reference's FP64 bisection, ESS and log-sum-exp on the same stage-0 energies."""
+    spec = getattr(W, cfg)(0)
+    say("stage full size", cfg, P)
+    s = native.Sampler(spec, native.options(seed=11, n_particles=P, n_moves=n, waste_free=wf))
+    e0 = {K: s.particles(K)[1].astype(np.float64) for K in range(spec.k_min, spec.k_max + 1)}
+    s.step()
+    for K in range(spec.k_min, spec.k_max + 1):
+        tr = s.trace(K)
+        d_ref = orc.next_delta(e0[K], 0.0, 0.5, 50)
+        d_gpu = tr["beta"][0]
+        assert delta_ok(orc, e0[K], 0.0, d_gpu, d_ref), (K, d_gpu, d_ref)
+        ess_ref, lse_ref = orc.ess(e0[K], d_gpu)
+        assert tr["ess"][0] == pytest.approx(ess_ref, rel=1e-10)
+        C = energy_constant(spec)
+        # log Z after one stage = LSE - ln P (energies without the constant) - delta * C
+        assert tr["logz"][0] == pytest.approx(lse_ref - math.log(P) - d_gpu * C, rel=1e-12, abs=1e-9)
+    s.close()
