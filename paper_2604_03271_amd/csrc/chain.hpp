@@ -188,14 +188,13 @@ __global__ void __launch_bounds__(256) k_energy(const GroupDesc* __restrict__ gr
 // Waves per SIMD the register allocator is asked to leave room for: the cached
 // point state grows with PPL (x, D, G, Gn per point, and y for Poisson counts);
 // these limits are the largest that compile without spilling on gfx950.
-template <int NZ, int PPL>
-constexpr int move_min_waves() {
-    if constexpr (NZ == SMC_NOISE_GAUSS) return PPL <= 12 ? 5 : (PPL <= 16 ? 4 : (PPL <= 20 ? 3 : 2));
-    else return PPL <= 8 ? 5 : (PPL <= 12 ? 4 : (PPL <= 16 ? 3 : 2));
+constexpr int move_min_waves(int noise, int points) {
+    return noise == SMC_NOISE_GAUSS ? (points <= 12 ? 5 : (points <= 16 ? 4 : (points <= 20 ? 3 : 2)))
+                                    : (points <= 8 ? 5 : (points <= 12 ? 4 : (points <= 16 ? 3 : 2)));
 }
 
 template <int PK, int NZ, int L, int WPC, int PPL>
-__global__ void __launch_bounds__(256, move_min_waves<NZ, PPL>()) k_move(const GroupDesc* __restrict__ groups,
+__global__ void __launch_bounds__(256, move_min_waves(NZ, PPL)) k_move(const GroupDesc* __restrict__ groups,
                                               const MoveWork* __restrict__ work) {
     using CS = ChainState<PK, NZ, L, WPC, PPL>;
     constexpr int LC = CS::LC;
