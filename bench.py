@@ -66,6 +66,63 @@ def cpu_baseline(spec, K, seconds_target=12.0):
                       f"{ne} likelihood evaluations of N={spec.n} points, {dt:.2f} s"}
 
 
+def batched(native, workloads, n_spectra, P=8192, plain_sample=4):
+    """Config 4: n_spectra uneven spectra, every K = 1..8, in one pool (captured stage replayed).
+    The plain comparator runs a few of the same spectra one at a time, one K at a time."""
+    import torch
+    specs = workloads.config4(n_spectra=n_spectra)
+    opt = native.options(n_particles=P, n_moves=16, waste_free=True, seed=3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    native.smc_batch_run(specs, opt)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tp = 0.0
+    for sp in specs[:plain_sample]:
+        s = native.Sampler(sp, native.options(n_particles=P, n_moves=16, waste_free=True, seed=3, plain=True))
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        s.run()
+        torch.cuda.synchronize()
+        tp += time.perf_counter() - ts
+        s.close()
+    return {"workload": f"config-4 batch: {n_spectra} spectra, N~U{{200..4000}}, Gaussian/pseudo-Voigt, "
+                        f"K=1..8, P={P}, waste-free n=16",
+            "spectra_per_s": n_spectra / dt, "batch_s": dt,
+            "plain_gpu_spectra_per_s": plain_sample / tp,
+            "plain_note": f"same kernels, one spectrum and one K at a time, measured on {plain_sample} of them"}
+
+
+def served(native, workloads, n_arrivals, rate, budget=64 << 30):
+    """Config 5: Poisson(rate) arrivals, 70% config-1-shaped and 30% config-2-shaped requests,
+    submitted in real time to the continuous-batching server."""
+    trace = workloads.config5_trace(n_arrivals=n_arrivals, rate=rate)
+    o1 = native.options(n_particles=512, n_moves=10, waste_free=False, seed=5)
+    o2 = native.options(n_particles=65536, n_moves=16, waste_free=True, seed=5)
+    srv = native.Server(budget, o1)
+    got, lat = {}, []
+    t0 = time.perf_counter()
+    i = 0
+    while len(got) < n_arrivals:
+        now = time.perf_counter() - t0
+        while i < n_arrivals and trace[i][0] <= now:
+            sp = trace[i][1]
+            st = srv.submit(sp, i, o1 if sp.n == 201 else o2)
+            assert st == 0, st
+            i += 1
+        for r in srv.poll(1):
+            got[r["id"]] = r
+            lat.append(r["latency_s"])
+    dur = time.perf_counter() - t0
+    srv.close()
+    lat = np.array(lat)
+    return {"workload": f"config-5 stream: {n_arrivals} Poisson({rate}/s) arrivals, 70% config-1 shape "
+                        "(P=512, standard n=10), 30% config-2 shape (P=65536, waste-free n=16)",
+            "spectra_per_s": n_arrivals / dur, "duration_s": dur,
+            "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+            "offered_per_s": rate}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +131,9 @@ def main():
     ap.add_argument("--particles", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--batch", type=int, default=0, help="also run the config-4 batch with this many spectra")
+    ap.add_argument("--serve", type=int, default=0, help="also serve this many config-5 arrivals")
+    ap.add_argument("--rate", type=float, default=200.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the sampler's groups are independent and this build "
@@ -155,6 +215,10 @@ def main():
         out["plain_gpu"] = {"spectra_per_s": 1.0 / dt, "evals_per_s": sp.evaluations() * spec.n / dt,
                             "note": "same kernels, one K at a time, one launch per K per stage"}
         sp.close()
+    if args.batch:
+        out["batched"] = batched(native, workloads, args.batch)
+    if args.serve:
+        out["served"] = served(native, workloads, args.serve, args.rate)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, 5)
     s.close()

@@ -194,8 +194,9 @@ typedef struct {
  * need fits mem_budget_bytes, join the pool at the next stage boundary and leave it when
  * every K is done.  defaults supplies P, n, mode, rho, seed and stream. */
 smc_status smc_server_create(smc_server** out, uint64_t mem_budget_bytes, const smc_options* defaults);
-/* Queue a request (the problem's arrays are copied).  SMC_EBUDGET if it can never fit. */
-smc_status smc_server_submit(smc_server* s, const smc_problem* prob, uint64_t request_id);
+/* Queue a request (the problem's arrays are copied) with its own options (NULL = the server's
+ * defaults; the stream field is ignored).  SMC_EBUDGET if it can never fit the budget. */
+smc_status smc_server_submit(smc_server* s, const smc_problem* prob, const smc_options* opt, uint64_t request_id);
 /* Collect up to cap finished results, waiting at most wait_ms (0 = poll). */
 smc_status smc_server_poll(smc_server* s, smc_result* out, int32_t cap, int32_t* n_out, int32_t wait_ms);
 /* Bytes of device particle state a request of this problem would hold. */

@@ -74,6 +74,7 @@ struct BlockAllocator {
 struct Entry {
     uint64_t id = 0;
     Spectrum spec;
+    smc_options opt{};
     Tile tile{};
     double econst = 0.0;
     int ng = 0;
@@ -313,6 +314,7 @@ extern "C" smc_status smc_batch_run(const smc_problem* probs, int32_t n, const s
     for (int i = 0; i < n; ++i) {
         entries[i] = std::make_unique<Entry>();
         Entry& e = *entries[i];
+        e.opt = *opt;
         e.spec.assign(probs[i]);
         e.ng = probs[i].k_max - probs[i].k_min + 1;
         e.tile = entry_tile(probs[i], *opt);
@@ -450,7 +452,7 @@ smc_status smc_server::tick() {
             size_t off = 0;
             if (!alloc.alloc(e.bytes, off)) break;
             e.off = off;
-            if (!carve_entry(e, opt, static_cast<char*>(dmem) + off)) {
+            if (!carve_entry(e, e.opt, static_cast<char*>(dmem) + off)) {
                 alloc.release(off, e.bytes);
                 smc_result r{};
                 r.request_id = e.id;
@@ -533,8 +535,8 @@ smc_status smc_server::tick() {
         }
         gi += e.ng;
     }
+    active.swap(keep_active);  // every still-running entry was moved into keep_active
     if (retired) {
-        active.swap(keep_active);
         cv_done.notify_all();
         std::vector<Entry*> ptrs;
         for (auto& ep : active) ptrs.push_back(ep.get());
@@ -599,19 +601,25 @@ extern "C" smc_status smc_server_create(smc_server** out, uint64_t mem_budget_by
     return SMC_OK;
 }
 
-extern "C" smc_status smc_server_submit(smc_server* sv, const smc_problem* prob, uint64_t request_id) {
+extern "C" smc_status smc_server_submit(smc_server* sv, const smc_problem* prob, const smc_options* opt,
+                                        uint64_t request_id) {
     if (!sv || !prob) return SMC_EINVAL;
-    smc_status st = validate(prob, &sv->opt);
+    smc_options o = opt ? *opt : sv->opt;
+    o.hip_stream = nullptr;
+    o.plain = 0;
+    o.profile = 0;
+    smc_status st = validate(prob, &o);
     if (st != SMC_OK) return st;
     if (prob->k_max - prob->k_min + 1 > 32) return SMC_EINVAL;
-    if (!entry_tile(*prob, sv->opt).valid) return SMC_EINVAL;
+    if (!entry_tile(*prob, o).valid) return SMC_EINVAL;
     auto e = std::make_unique<Entry>();
     e->id = request_id;
+    e->opt = o;
     e->spec.assign(*prob);
     e->ng = prob->k_max - prob->k_min + 1;
-    e->tile = entry_tile(*prob, sv->opt);
+    e->tile = entry_tile(*prob, o);
     e->econst = energy_constant(e->spec.prob);
-    e->bytes = align256(entry_bytes(*prob, sv->opt));
+    e->bytes = align256(entry_bytes(*prob, o));
     e->t_submit = std::chrono::steady_clock::now();
     if (e->bytes > sv->budget) return SMC_EBUDGET;
     {

@@ -104,7 +104,7 @@ _SIGNATURES = {
     "smc_strerror": (ctypes.c_char_p, [c_i32]),
     "smc_batch_run": (c_i32, [P(smc_problem), c_i32, P(smc_options), P(c_d)]),
     "smc_server_create": (c_i32, [P(c_vp), c_u64, P(smc_options)]),
-    "smc_server_submit": (c_i32, [c_vp, P(smc_problem), c_u64]),
+    "smc_server_submit": (c_i32, [c_vp, P(smc_problem), P(smc_options), c_u64]),
     "smc_server_poll": (c_i32, [c_vp, P(smc_result), c_i32, P(c_i32), c_i32]),
     "smc_server_request_bytes": (c_u64, [P(smc_problem), P(smc_options)]),
     "smc_server_destroy": (None, [c_vp]),
@@ -358,6 +358,49 @@ def smc_batch_run(specs: Sequence, opt: smc_options) -> list:
         res.append(out[off:off + n].copy())
         off += n
     return res
+
+
+class Server:
+    """Continuous-batching server (smc_server_*): submit spectra, poll results."""
+
+    def __init__(self, budget_bytes: int, defaults: smc_options):
+        self.srv = c_vp()
+        check(lib().smc_server_create(ctypes.byref(self.srv), budget_bytes, ctypes.byref(defaults)),
+              "smc_server_create")
+        self._keep = {}
+
+    def submit(self, spec, request_id: int, opt: Optional[smc_options] = None) -> int:
+        pr = Problem(spec)
+        self._keep[request_id] = (pr, opt)
+        return lib().smc_server_submit(self.srv, pr.ref, ctypes.byref(opt) if opt is not None else None,
+                                       request_id)
+
+    def poll(self, wait_ms: int = 0, cap: int = 256) -> list:
+        res = (smc_result * cap)()
+        n = c_i32()
+        st = lib().smc_server_poll(self.srv, res, cap, ctypes.byref(n), wait_ms)
+        if st not in (SMC_OK, SMC_EAGAIN):
+            check(st, "smc_server_poll")
+        out = []
+        for i in range(n.value):
+            r = res[i]
+            nk = r.k_max - r.k_min + 1
+            out.append({"id": int(r.request_id), "status": int(r.status), "k_min": int(r.k_min),
+                        "logz": np.array(r.logz[:max(nk, 0)]), "best_k": int(r.best_k),
+                        "latency_s": float(r.latency_s), "n_stages": int(r.n_stages)})
+            self._keep.pop(int(r.request_id), None)
+        return out
+
+    def request_bytes(self, spec, opt: smc_options) -> int:
+        return int(lib().smc_server_request_bytes(Problem(spec).ref, ctypes.byref(opt)))
+
+    def close(self):
+        if self.srv:
+            lib().smc_server_destroy(self.srv)
+            self.srv = None
+
+    def __del__(self):
+        self.close()
 
 
 # ---------------------------------------------------------------------------- per-kernel hooks

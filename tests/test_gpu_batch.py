@@ -82,7 +82,7 @@ def test_server_equals_alone():
     probs = [native.Problem(sp) for sp in specs]
     try:
         for i, pr in enumerate(probs):
-            assert native.lib().smc_server_submit(srv, pr.ref, 100 + i) == 0
+            assert native.lib().smc_server_submit(srv, pr.ref, None, 100 + i) == 0
             time.sleep(0.01 * i)   # arrivals spread over time: later ones join a running pool
         res = _server_results(srv, len(specs))
     finally:
@@ -106,12 +106,40 @@ def test_server_admission_under_small_budget():
     srv = _server(int(need * 1.5), kw)   # one request at a time fits
     try:
         for i, pr in enumerate(probs):
-            assert native.lib().smc_server_submit(srv, pr.ref, i) == 0
+            assert native.lib().smc_server_submit(srv, pr.ref, None, i) == 0
         big = native.Problem(W.config2(0))
-        assert native.lib().smc_server_submit(srv, big.ref, 99) == native.SMC_EBUDGET
+        assert native.lib().smc_server_submit(srv, big.ref, None, 99) == native.SMC_EBUDGET
         res = _server_results(srv, len(probs))
     finally:
         native.lib().smc_server_destroy(srv)
     assert sorted(res) == list(range(len(probs)))
     for i, sp in enumerate(specs):
         assert np.array_equal(np.asarray(res[i][1]), _alone(sp, kw))
+
+
+def test_server_mixed_shapes_equal_alone():
+    """Config-1-shaped (standard, n=10) and config-2-shaped (waste-free, n=16) requests with
+    their own options in one pool; every result equals the same request run alone."""
+    torch_cuda()
+    say("server mixed shapes")
+    srv = native.Server(4 << 30, native.options(n_particles=512, n_moves=10, waste_free=False, seed=9))
+    reqs = []
+    for i in range(4):
+        if i % 2 == 0:
+            sp, kw = W.config1(200 + i), dict(n_particles=512, n_moves=10, waste_free=False, seed=9)
+        else:
+            sp, kw = W.config2(200 + i), dict(n_particles=2048, n_moves=16, waste_free=True, seed=9)
+            sp.k_max = 4
+        sp.uid = 700 + i
+        reqs.append((sp, kw))
+        assert srv.submit(sp, i, native.options(**kw)) == 0
+    got = {}
+    t0 = time.time()
+    while len(got) < len(reqs) and time.time() - t0 < 120:
+        for r in srv.poll(200):
+            got[r["id"]] = r
+    srv.close()
+    assert len(got) == len(reqs)
+    for i, (sp, kw) in enumerate(reqs):
+        assert got[i]["status"] == 0
+        assert np.array_equal(got[i]["logz"], _alone(sp, kw))
