@@ -14,6 +14,11 @@ value = particle*point likelihood evaluations per second: every likelihood
 evaluation (one per particle at stage 0, one per Metropolis proposal inside
 the prior's support) covers N points.
 
+--workload paper-k3 | paper-k10 | paper-k30 times the paper's own Gaussian-peak
+spectra instead (App. B: N = 300 / 1000 / 3000, n = 10 / 10 / 100 moves per
+temperature, free energy at the true K only), by default at the largest
+particle counts the paper runs (10^6, and 3 x 10^6 for K = 30).
+
 Prints one JSON line.
 """
 import argparse
@@ -123,17 +128,37 @@ def served(native, workloads, n_arrivals, rate, budget=64 << 30):
             "offered_per_s": rate}
 
 
+def _workload(name, native_options, workloads, particles):
+    """(spectrum, options, description) of a named workload."""
+    if name == "xps-pv":
+        spec = workloads.config2(0)
+        P, n = particles or 65536, 16
+        desc = (f"XPS-like spectrum N=1001, 5 pseudo-Voigt peaks + linear background, sigma=0.02, "
+                f"K=1..8, P={P} per K, waste-free n={n}")
+    else:
+        K = int(name.split("-k")[1])
+        spec = workloads.paper_gaussian(K)
+        n = workloads.PAPER_MOVES[K]
+        P = particles or (3_000_000 if K == 30 else 1_000_000)
+        desc = (f"paper Gaussian-peak spectrum K={K}, N={spec.n}, sigma={spec.sigma}, free energy at K={K}, "
+                f"P={P}, waste-free n={n}")
+    return spec, native_options(n_particles=P, n_moves=n, waste_free=True, seed=0, profile=True), desc
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--particles", type=int, default=65536)
+    ap.add_argument("--workload", default="xps-pv", choices=["xps-pv", "paper-k3", "paper-k10", "paper-k30"])
+    ap.add_argument("--particles", type=int, default=0, help="particles per K (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--batch", type=int, default=0, help="also run the config-4 batch with this many spectra")
     ap.add_argument("--serve", type=int, default=0, help="also serve this many config-5 arrivals")
     ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="also run one device-to-device copy of this many bytes (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the sampler's groups are independent and this build "
@@ -144,9 +169,16 @@ def main():
     from paper_2604_03271_amd import native, workloads
 
     torch.cuda.init()
-    spec = workloads.config2(0)
-    P, n = args.particles, 16
-    opt = native.options(n_particles=P, n_moves=n, waste_free=True, seed=0, profile=True)
+    if args.copy_bytes:
+        src = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    spec, opt, desc = _workload(args.workload, native.options, workloads, args.particles)
+    P, n = opt.n_particles, opt.n_moves
+    ks = range(spec.k_min, spec.k_max + 1)
     s = native.Sampler(spec, opt)
     for w in range(args.warmup):
         s.reset(1000 + w).run()
@@ -162,7 +194,7 @@ def main():
         evals += s.evaluations()
         lat.append(time.perf_counter() - ts)
         logz.append(s.log_evidence())
-        stages.append(max(s.stage_info(K)[0] for K in range(1, 9)))
+        stages.append(max(s.stage_info(K)[0] for K in ks))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof1 = s.profile()
@@ -171,7 +203,7 @@ def main():
 
     # roofline of the dominant kernel (the MH move): algorithmic lane-instructions per launch
     # over the launch's average duration from HIP events on the library's stream
-    move_evals = evals - args.steps * P * 8
+    move_evals = evals - args.steps * P * len(ks)
     key = (spec.peak_kind, spec.noise_kind)
     per_unit = VALU_PER_UNIT[key] + TRANS_COST * TRANS_PER_UNIT[key]
     launches = prof1["move_launches"] - prof0["move_launches"]
@@ -195,14 +227,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "XPS-like spectrum N=1001, 5 pseudo-Voigt peaks + linear background, sigma=0.02, "
-                               "K=1..8, P=65536 per K, waste-free n=16",
-                   "n_points": spec.n, "k_range": [1, 8], "particles_per_k": P, "n_moves": n,
+        "config": {"workload": desc,
+                   "n_points": spec.n, "k_range": [spec.k_min, spec.k_max], "particles_per_k": P, "n_moves": n,
                    "parallelism": "single GPU, all K in one launch"},
         "spectra_per_s": args.steps / elapsed,
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "stages_max": int(np.max(stages)),
-        "best_k": int(np.argmax(np.mean(logz, 0)) + 1),
+        "best_k": int(np.argmax(np.mean(logz, 0)) + spec.k_min),
         "roofline": roofline,
     }
     if not args.no_plain:
@@ -220,7 +251,7 @@ def main():
     if args.serve:
         out["served"] = served(native, workloads, args.serve, args.rate)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(spec, 5)
+        out["cpu_baseline"] = cpu_baseline(spec, 5 if args.workload == "xps-pv" else spec.truth["K"])
     s.close()
     print(json.dumps(out), flush=True)
 

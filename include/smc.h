@@ -92,7 +92,7 @@ typedef struct {
 } smc_problem;
 
 typedef struct {
-    int32_t n_particles;   /* P per candidate K, >= 2 */
+    int32_t n_particles;   /* P per candidate K, >= 2, with P * dim(k_max) <= 2^31 - 1 */
     int32_t n_moves;       /* n: MCMC sweeps per stage (standard) or chain length (waste-free) */
     int32_t waste_free;    /* 1: resample P/n chains and keep every post-sweep state (needs P % n == 0) */
     int32_t bisect_iters;  /* halvings of the temperature bisection (paper reading: 50) */

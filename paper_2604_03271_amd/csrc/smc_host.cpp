@@ -83,6 +83,9 @@ smc_status validate(const smc_problem* p, const smc_options* o) {
         if (!prior_ok(p->bg_prior[q])) return SMC_EINVAL;
     if (o->n_particles < 2 || o->n_moves < 1) return SMC_EINVAL;
     if (o->waste_free && (o->n_particles % o->n_moves) != 0) return SMC_EINVAL;
+    // device tables index component-major particle arrays with 32-bit offsets
+    const int64_t dmax = static_cast<int64_t>(p->k_max) * np + params_bg(p->bg_kind);
+    if (dmax * o->n_particles > INT32_MAX) return SMC_EINVAL;
     if (!(o->ess_frac > 0.0 && o->ess_frac < 1.0)) return SMC_EINVAL;
     if (o->bisect_iters < 1 || o->bisect_iters > 200 || o->max_stages < 1) return SMC_EINVAL;
     if (o->lanes_per_chain != 0 && o->lanes_per_chain != 16 && o->lanes_per_chain != 32 &&

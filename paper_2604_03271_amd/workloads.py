@@ -222,3 +222,43 @@ def random_spectrum(rng: np.random.Generator, n: int, peak_kind: str, bg_kind: s
            "linear": [("uniform", -1.0, 100.0), ("uniform", -1.0, 1.0)]}[bg_kind]
     return Spectrum(x, y, peak_kind, bg_kind, noise_kind, sigma, pp, bgp, 1, 4,
                     truth={"K": k_true, "peaks": peaks, "bg": bg})
+
+
+# --- the paper's own Gaussian-peak workloads (App. B) ------------------------------------
+# Truth values of Tables spectral_true_K3, spectral_true_K10 and spectral_true_K30 (A_k, mu_k, b_k),
+# conditions of Table spectral_true_params (N, x range, sigma) and priors of Table spectral_priors
+# (Ga(5,5) amplitude; N(1.5, 0.2) centre for K = 3, U(0, x_max) otherwise; Ga(5, 0.04) width,
+# shape-rate; the normal's second argument is a variance).  The paper does not print its noise
+# draw, so the observations are regenerated here with this module's own seed.
+
+PAPER_TRUTH = {
+    3: [(0.587, 1.210, 95.689), (1.522, 1.455, 146.837), (1.183, 1.703, 164.469)],
+    10: [(1.049, 0.558, 114.335), (1.215, 2.082, 194.467), (1.103, 2.804, 152.185), (1.045, 3.549, 141.466),
+         (0.924, 4.678, 126.456), (1.146, 5.633, 177.423), (0.938, 7.098, 145.615), (1.392, 7.418, 156.843),
+         (1.464, 8.625, 101.879), (0.883, 9.158, 161.764)],
+    30: [(0.576, 0.486, 105.313), (1.280, 1.065, 130.885), (0.938, 2.378, 159.259), (1.223, 2.814, 123.512),
+         (1.478, 4.815, 196.497), (1.038, 5.375, 194.505), (1.001, 6.277, 184.840), (0.572, 7.822, 147.232),
+         (0.768, 8.005, 184.148), (1.000, 9.661, 113.111), (1.179, 9.881, 130.873), (1.304, 11.301, 146.300),
+         (0.881, 12.139, 174.185), (0.566, 13.939, 148.583), (0.788, 15.030, 113.688), (1.410, 15.401, 134.354),
+         (0.713, 16.752, 132.443), (0.952, 17.446, 130.042), (1.431, 18.670, 116.550), (0.525, 19.274, 141.490),
+         (1.101, 19.987, 144.812), (1.450, 20.959, 177.490), (0.730, 22.615, 179.639), (1.048, 24.174, 152.239),
+         (1.409, 24.581, 146.063), (0.633, 25.343, 177.821), (1.023, 27.074, 188.729), (1.250, 27.571, 167.492),
+         (1.169, 28.530, 180.048), (0.968, 29.576, 193.911)],
+}
+PAPER_CONDITIONS = {3: (300, 3.0, 0.1), 10: (1000, 10.0, 0.1), 30: (3000, 30.0, 0.05)}
+PAPER_MOVES = {3: 10, 10: 10, 30: 100}   # MCMC steps per temperature used with the SMCS
+
+
+def paper_gaussian(K: int, index: int = 0, k_span: int = 0) -> Spectrum:
+    """The paper's artificial Gaussian-peak spectrum with K = 3, 10 or 30 true peaks.  The paper
+    estimates the free energy at the true K (Sec. III.A.2), so the candidate range is K alone;
+    k_span > 0 widens it to K-k_span..K+k_span."""
+    n, xmax, sigma = PAPER_CONDITIONS[K]
+    rng = np.random.default_rng(1000 * 6 + 100 * K + index)
+    x = f32(np.linspace(0.0, xmax, n))
+    peaks = PAPER_TRUTH[K]
+    y = f32(_synth(x, "gauss", peaks) + sigma * rng.standard_normal(n))
+    mu_prior = ("normal", 1.5, float(np.sqrt(0.2))) if K == 3 else ("uniform", 0.0, xmax)
+    pri = [("gamma", 5.0, 5.0), mu_prior, ("gamma", 5.0, 0.04)]
+    return Spectrum(x, y, "gauss", "none", "gauss", sigma, pri, [], max(1, K - k_span), K + k_span,
+                    truth={"K": K, "peaks": peaks}, uid=6000 + 100 * K + index)
