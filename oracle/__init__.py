@@ -108,6 +108,9 @@ def lib():
             "or_step_sizes": (None, [PD, I32, I32, PD, PD]),
             "or_update_lambda": (None, [PD, PI, I32, D]),
             "or_run": (I32, [PP, I32, ctypes.POINTER(_Options), ctypes.POINTER(_Result)]),
+            "or_relabel_by_centre": (None, [PD, I32, I32, I32, I32]),
+            "or_posterior_summary": (I32, [PD, I32, I32, I32, I32, PD, I32, PD, PD]),
+            "or_posterior_k": (None, [PD, I32, PD]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -314,3 +317,31 @@ def run(prob: Problem, K: int, n_particles: int, n_moves: int, waste_free: bool,
                      beta=tr["beta"][:ns].copy(), ess=tr["ess"][:ns].copy(), logz=tr["logz"][:ns].copy(),
                      accept=tr["accept"][:ns].copy(),
                      theta=None if th is None else th[:, :d], energy=E)
+
+
+def relabel_by_centre(theta, n_peaks: int, np_: int) -> np.ndarray:
+    """Each particle's peaks sorted by centre (stable); theta is [P][d]."""
+    th = np.array(theta, dtype=np.float64, order="C", copy=True)
+    lib().or_relabel_by_centre(_pd(th), th.shape[0], th.shape[1], n_peaks, np_)
+    return th
+
+
+def posterior_summary(theta, probs, relabel: int = 0, np_: int = 3):
+    """(mean[d], quantiles[len(probs)][d]) of an equally weighted sample theta [P][d]."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    P, d = th.shape
+    pr = np.ascontiguousarray(probs, dtype=np.float64)
+    mean = np.zeros(d)
+    q = np.zeros((max(len(pr), 1), d))
+    st = lib().or_posterior_summary(_pd(th), P, d, relabel, np_, _pd(pr), len(pr), _pd(mean), _pd(q))
+    if st != 0:
+        raise ValueError(f"or_posterior_summary: {st}")
+    return mean, q[:len(pr)]
+
+
+def posterior_k(logz) -> np.ndarray:
+    """p(K|D) under a uniform prior over the candidates."""
+    lz = np.ascontiguousarray(logz, dtype=np.float64)
+    out = np.zeros(len(lz))
+    lib().or_posterior_k(_pd(lz), len(lz), _pd(out))
+    return out

@@ -554,3 +554,85 @@ done:
     free(lambda); free(step); free(acc);
     return status;
 }
+
+/* ------------------------------------------------------------------------
+ * Posterior summaries (Sec. III: the posterior mean and the endpoints of the
+ * 95% and 99% credible intervals; Sec. II.A: p(K|D) from the free energies).
+ *
+ * After the final move at beta = 1 the P particles are an equally weighted
+ * sample of the posterior of one K.  For each component j:
+ *   mean_j     = (1/P) sum_i theta_ij
+ *   quantile_q = x_(r), r = max(1, ceil(q P)), x_(1) <= ... <= x_(P) the
+ *                sorted sample: the smallest sample value whose empirical
+ *                CDF reaches q (inverse of the empirical CDF).
+ * A credible interval at level c is (quantile_{(1-c)/2}, quantile_{(1+c)/2}).
+ *
+ * The prior is exchangeable in the peaks, so the per-peak marginals are only
+ * meaningful after the peaks of every particle are put in one order.  With
+ * relabel > 0 each particle's relabel peaks (np parameters each, centre at
+ * offset 1) are first sorted by centre; equal centres keep their index order.
+ * theta is particle-major, [P][d].
+ * ------------------------------------------------------------------------ */
+static int cmp_double(const void* a, const void* b)
+{
+    double x = *(const double*)a, y = *(const double*)b;
+    return (x > y) - (x < y);
+}
+
+void or_relabel_by_centre(double* theta, int P, int d, int n_peaks, int np)
+{
+    (void)d;
+    for (int i = 0; i < P; ++i) {
+        double* t = theta + (size_t)i * d;
+        /* stable insertion sort of the peak blocks by their centre */
+        for (int k = 1; k < n_peaks; ++k) {
+            double blk[8];
+            memcpy(blk, t + k * np, sizeof(double) * (size_t)np);
+            int m = k;
+            while (m > 0 && t[(m - 1) * np + 1] > blk[1]) {
+                memcpy(t + m * np, t + (m - 1) * np, sizeof(double) * (size_t)np);
+                --m;
+            }
+            memcpy(t + m * np, blk, sizeof(double) * (size_t)np);
+        }
+    }
+}
+
+int or_posterior_summary(const double* theta_in, int P, int d, int relabel, int np,
+                         const double* probs, int n_probs, double* mean, double* quant)
+{
+    if (P < 1 || d < 1 || n_probs < 0 || np < 2 || np > 8 || relabel * np > d) return -1;
+    double* theta = (double*)malloc(sizeof(double) * (size_t)P * d);
+    double* col = (double*)malloc(sizeof(double) * (size_t)P);
+    if (!theta || !col) { free(theta); free(col); return -2; }
+    memcpy(theta, theta_in, sizeof(double) * (size_t)P * d);
+    if (relabel > 0) or_relabel_by_centre(theta, P, d, relabel, np);
+    for (int j = 0; j < d; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < P; ++i) {
+            col[i] = theta[(size_t)i * d + j];
+            s += col[i];
+        }
+        mean[j] = s / (double)P;
+        qsort(col, (size_t)P, sizeof(double), cmp_double);
+        for (int q = 0; q < n_probs; ++q) {
+            double r = ceil(probs[q] * (double)P);
+            if (r < 1.0) r = 1.0;
+            if (r > (double)P) r = (double)P;
+            quant[(size_t)q * d + j] = col[(int)r - 1];
+        }
+    }
+    free(theta); free(col);
+    return 0;
+}
+
+/* p(K|D) for a uniform prior over the candidates: exp(log Z_K) normalised, by
+ * the log-sum-exp of the log evidences (Eq. (free_energy_def): F = -log Z). */
+void or_posterior_k(const double* logz, int n, double* out)
+{
+    double m = -INFINITY;
+    for (int k = 0; k < n; ++k) if (logz[k] > m) m = logz[k];
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) s += exp(logz[k] - m);
+    for (int k = 0; k < n; ++k) out[k] = exp(logz[k] - m) / s;
+}

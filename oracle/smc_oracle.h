@@ -73,4 +73,9 @@ void or_step_sizes(const double* theta, int M, int d, const double* lambda, doub
 void or_update_lambda(double* lambda, const int32_t* acc, int d, double proposals);
 int or_run(const or_problem* p, int K, const or_options* o, or_result* res);
 
+void or_relabel_by_centre(double* theta, int P, int d, int n_peaks, int np);
+int or_posterior_summary(const double* theta, int P, int d, int relabel, int np,
+                         const double* probs, int n_probs, double* mean, double* quant);
+void or_posterior_k(const double* logz, int n, double* out);
+
 #endif
