@@ -157,6 +157,30 @@ smc_status smc_trace(const smc_ctx* ctx, int32_t K, double* beta, double* ess, d
  * constant).  cap is the capacity of theta_soa in floats. */
 smc_status smc_particles(const smc_ctx* ctx, int32_t K, float* theta_soa, float* energy, int64_t cap);
 
+/* ---------------- posterior summaries (Sec. III; Eq. (free_energy_def)) ---------------- */
+
+#define SMC_MAX_PROBS 8
+
+/* Summaries of candidate K from its final population (beta = 1, P equally weighted
+ * particles), computed on the device.  For each component j of the K-peak model (d of them):
+ *   mean[j]            = (1/P) sum_i theta_ij, summed in FP64;
+ *   quant[t * d + j]   = the sample value of rank max(1, ceil(probs[t] * P)) in ascending order
+ *                        (inverse empirical CDF), exact, for t < n_probs <= SMC_MAX_PROBS.
+ * A credible interval at level c is (q_{(1-c)/2}, q_{(1+c)/2}): probs {0.025, 0.975} give the
+ * 95% interval, {0.005, 0.995} the 99% one.  relabel != 0 first sorts every particle's peaks
+ * by centre (stable), since the prior is exchangeable in the peaks and per-peak summaries
+ * need one labelling; the stored particles are not changed.  mean [d] and quant
+ * [n_probs * d] are host arrays.  Allocates and frees a device buffer of d * P floats when
+ * relabel != 0.  Errors: SMC_EINVAL (bad K, probabilities outside [0, 1], n_probs out of
+ * range, NULL outputs), SMC_ESTATE (K has not reached beta = 1), SMC_EDEVICE. */
+smc_status smc_posterior_summary(smc_ctx* ctx, int32_t K, const double* probs, int32_t n_probs, int32_t relabel,
+                                 double* mean, double* quant);
+
+/* p(K | D) for K = k_min .. k_min + cap - 1 under a uniform prior over the candidates:
+ * exp(log Z_K) normalised by the log-sum-exp of the log evidences (F = -log Z), in FP64 on
+ * the host.  SMC_ESTATE if some K has not finished. */
+smc_status smc_posterior_k(const smc_ctx* ctx, double* out, int32_t cap);
+
 /* Dimension d of the K-peak model of the problem. */
 int32_t smc_dim(const smc_problem* prob, int32_t K);
 
@@ -228,6 +252,13 @@ smc_status smc_kernel_ess_bisect(const float* energy, int32_t P, double beta, do
  * with uniform r / 2^32 (integer-exact; see the reading above). */
 smc_status smc_kernel_resample(const double* weights, int32_t P, int32_t M, uint32_t r, int32_t* ancestors,
                                void* stream);
+
+/* Posterior summary kernels on caller buffers: theta (device) [d][P] FP32 component-major,
+ * optional relabelling of n_peaks peaks of np parameters (centre at offset 1; 0 = none),
+ * outputs as for smc_posterior_summary (host).  The device scratch (d*P floats when
+ * relabelling, plus the outputs) is allocated and freed inside.  hip_stream may be NULL. */
+smc_status smc_kernel_summary(const float* theta, int32_t d, int32_t P, int32_t n_peaks, int32_t np,
+                              const double* probs, int32_t n_probs, double* mean, double* quant, void* hip_stream);
 
 /* One MH move of candidate K at inverse temperature beta: M start states start_soa
  * (device) [d][M] with energies start_e [M], step sizes step (device) [d]; outputs

@@ -19,7 +19,7 @@ FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-I" + os.path.j
          "-I" + CSRC, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-pass-failed"]
 SOURCES = ["kernels_00.hip", "kernels_01.hip", "kernels_10.hip", "kernels_11.hip", "stage.hip",
-           "smc_host.cpp", "hooks.cpp", "batch.cpp"]
+           "summary.hip", "smc_host.cpp", "hooks.cpp", "batch.cpp"]
 
 
 def _compile(src, verbose):

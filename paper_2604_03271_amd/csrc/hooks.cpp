@@ -228,3 +228,10 @@ extern "C" smc_status smc_kernel_move(const smc_problem* prob, int32_t K, const 
         return SMC_EDEVICE;
     return finish(s);
 }
+
+extern "C" smc_status smc_kernel_summary(const float* theta, int32_t d, int32_t P, int32_t n_peaks, int32_t np,
+                                         const double* probs, int32_t n_probs, double* mean, double* quant,
+                                         void* hip_stream) {
+    return posterior_summary(theta, d, P, n_peaks, np, probs, n_probs, mean, quant,
+                             static_cast<hipStream_t>(hip_stream));
+}

@@ -25,6 +25,12 @@ struct Arena {
     void* take(size_t bytes);
 };
 
+// 0-based sample ranks of the requested quantiles, passed to the summary kernel by value.
+struct SummaryRanks {
+    int32_t n;
+    int32_t r[SMC_MAX_PROBS];
+};
+
 struct PendingCopy {
     void* dst;
     const void* src;
@@ -70,5 +76,12 @@ hipError_t launch_resample_hook(const double* W, int P, int M, uint32_t r, unsig
                                 hipStream_t s);
 hipError_t launch_draw(const GroupDesc* groups, int group, int64_t n_draws, hipStream_t s);
 hipError_t launch_draw_items(const GroupDesc* groups, const MoveWork* items, int n_items, hipStream_t s);
+
+// summary.hip
+hipError_t launch_relabel(const float* in, float* out, int P, int d, int n_peaks, int np, hipStream_t s);
+hipError_t launch_summary(const float* theta, int P, int d, const SummaryRanks& ranks, double* mean, float* quant,
+                          hipStream_t s);
+smc_status posterior_summary(const float* theta, int d, int P, int n_peaks, int np, const double* probs,
+                             int n_probs, double* mean, double* quant, hipStream_t s);
 
 }  // namespace smc

@@ -703,6 +703,31 @@ extern "C" smc_status smc_particles(const smc_ctx* c, int32_t K, float* theta_so
     return SMC_OK;
 }
 
+extern "C" smc_status smc_posterior_summary(smc_ctx* c, int32_t K, const double* probs, int32_t n_probs,
+                                            int32_t relabel, double* mean, double* quant) {
+    if (!c || K < c->kmin || K > c->kmax) return SMC_EINVAL;
+    const int gi = K - c->kmin;
+    if (c->states[gi].beta < 1.0) return SMC_ESTATE;
+    const GroupDesc& g = c->groups[gi];
+    const int n_peaks = relabel ? K : 0;
+    return posterior_summary(g.theta, g.d, g.P, n_peaks, g.np, probs, n_probs, mean, quant, c->stream);
+}
+
+extern "C" smc_status smc_posterior_k(const smc_ctx* c, double* out, int32_t cap) {
+    if (!c || !out || cap < 1) return SMC_EINVAL;
+    const int n = std::min(cap, c->ng);
+    std::vector<double> lz(n);
+    const smc_status st = smc_log_evidence(c, lz.data(), n);
+    if (st != SMC_OK) return st;
+    double m = -INFINITY;
+    for (double v : lz) m = std::max(m, v);
+    if (!std::isfinite(m)) return SMC_ENUMERIC;
+    double sum = 0.0;
+    for (double v : lz) sum += std::exp(v - m);
+    for (int i = 0; i < n; ++i) out[i] = std::exp(lz[i] - m) / sum;
+    return SMC_OK;
+}
+
 extern "C" void smc_free(smc_ctx* c) {
     if (!c) return;
     if (c->stream) hipStreamSynchronize(c->stream);

@@ -98,6 +98,9 @@ _SIGNATURES = {
     "smc_stage_info": (c_i32, [c_vp, c_i32, P(c_i32), P(c_d), P(c_d), P(c_d)]),
     "smc_trace": (c_i32, [c_vp, c_i32, P(c_d), P(c_d), P(c_d), P(c_d), c_i32, P(c_i32)]),
     "smc_particles": (c_i32, [c_vp, c_i32, P(ctypes.c_float), P(ctypes.c_float), c_i64]),
+    "smc_posterior_summary": (c_i32, [c_vp, c_i32, P(c_d), c_i32, c_i32, P(c_d), P(c_d)]),
+    "smc_posterior_k": (c_i32, [c_vp, P(c_d), c_i32]),
+    "smc_kernel_summary": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_i32, P(c_d), c_i32, P(c_d), P(c_d), c_vp]),
     "smc_dim": (c_i32, [P(smc_problem), c_i32]),
     "smc_energy_constant": (c_i32, [P(smc_problem), P(c_d)]),
     "smc_free": (None, [c_vp]),
@@ -292,6 +295,25 @@ def smc_particles(ctx, K: int, d: int, n_particles: int):
     return th[:d * n_particles].reshape(d, n_particles), e
 
 
+def _summary_out(d: int, probs):
+    pr = np.ascontiguousarray(probs, dtype=np.float64)
+    return pr, np.zeros(d, dtype=np.float64), np.zeros((max(len(pr), 1), d), dtype=np.float64)
+
+
+def smc_posterior_summary(ctx, K: int, d: int, probs, relabel: bool):
+    """(mean [d], quantiles [len(probs)][d]) of candidate K's final population."""
+    pr, mean, q = _summary_out(d, probs)
+    check(lib().smc_posterior_summary(ctx, K, _pd(pr), len(pr), int(bool(relabel)), _pd(mean), _pd(q)),
+          "smc_posterior_summary")
+    return mean, q[:len(pr)]
+
+
+def smc_posterior_k(ctx, n: int) -> np.ndarray:
+    out = np.zeros(n, dtype=np.float64)
+    check(lib().smc_posterior_k(ctx, _pd(out), n), "smc_posterior_k")
+    return out
+
+
 def smc_free(ctx) -> None:
     if ctx:
         lib().smc_free(ctx)
@@ -342,6 +364,12 @@ class Sampler:
 
     def particles(self, K: int):
         return smc_particles(self.ctx, K, self.problem.dim(K), self.opt.n_particles)
+
+    def posterior_summary(self, K: int, probs=(0.005, 0.025, 0.975, 0.995), relabel: bool = True):
+        return smc_posterior_summary(self.ctx, K, self.problem.dim(K), probs, relabel)
+
+    def posterior_k(self):
+        return smc_posterior_k(self.ctx, self.problem.c.k_max - self.problem.c.k_min + 1)
 
 
 # ---------------------------------------------------------------------------- batch / server
@@ -435,6 +463,14 @@ def smc_kernel_ess_bisect(energy, beta: float, rho: float = 0.5, iters: int = 50
 def smc_kernel_resample(weights, M: int, r: int, ancestors, stream=None) -> None:
     check(lib().smc_kernel_resample(_ptr(weights), weights.numel(), M, r, _ptr(ancestors), _stream_ptr(stream)),
           "smc_kernel_resample")
+
+
+def smc_kernel_summary(theta, d: int, P: int, probs, n_peaks: int = 0, np_: int = 3, stream=None):
+    """Summary kernels on a device tensor theta [d][P] (FP32, contiguous)."""
+    pr, mean, q = _summary_out(d, probs)
+    check(lib().smc_kernel_summary(_ptr(theta), d, P, n_peaks, np_, _pd(pr), len(pr), _pd(mean), _pd(q),
+                                   _stream_ptr(stream)), "smc_kernel_summary")
+    return mean, q[:len(pr)]
 
 
 def smc_kernel_move(problem: Problem, K: int, start, start_e, n: int, waste_free: bool, beta: float, seed: int,

@@ -99,3 +99,21 @@ def test_hooks_reject_bad_arguments():
     assert L.smc_kernel_resample(None, 10, 10, 0, None, None) == native.SMC_EINVAL
     assert L.smc_kernel_philox(None, 0, 0, None, -1, None) == native.SMC_EINVAL
     assert L.smc_kernel_philox(None, 0, 0, None, 0, None) == native.SMC_OK
+
+
+def test_summary_rejects_bad_arguments():
+    """Argument checks run on the host before any device work."""
+    L = native.lib()
+    D = ctypes.c_double
+    probs = (D * 2)(0.025, 0.975)
+    bad = (D * 1)(1.5)
+    mean = (D * 4)()
+    quant = (D * 8)()
+    fake = ctypes.c_void_p(16)   # never dereferenced: the checks fail first
+    assert L.smc_kernel_summary(None, 4, 10, 0, 3, probs, 2, mean, quant, None) == native.SMC_EINVAL
+    assert L.smc_kernel_summary(fake, 4, 10, 0, 3, bad, 1, mean, quant, None) == native.SMC_EINVAL
+    assert L.smc_kernel_summary(fake, 4, 10, 0, 3, probs, 9, mean, quant, None) == native.SMC_EINVAL
+    assert L.smc_kernel_summary(fake, 4, 10, 2, 3, probs, 2, mean, quant, None) == native.SMC_EINVAL  # 2*3 > d
+    assert L.smc_kernel_summary(fake, 4, 0, 0, 3, probs, 2, mean, quant, None) == native.SMC_EINVAL
+    assert L.smc_posterior_summary(None, 1, probs, 2, 0, mean, quant) == native.SMC_EINVAL
+    assert L.smc_posterior_k(None, mean, 4) == native.SMC_EINVAL
