@@ -124,17 +124,24 @@ DevPrior dev_prior(const smc_prior& p) {
 // (2048 waves on 256 CUs); otherwise the largest lane count that fits.
 Tile choose_tile(int n_points, int64_t chains, int forced_lanes) {
     Tile t{};
+    // Preference: chains inside one wavefront with at most 16 points per lane (the move
+    // kernel keeps 4+ waves per SIMD there), then up to 32 points per lane (2-3 waves),
+    // then four wavefronts per chain (a cross-wave LDS reduction per proposal).  Within a
+    // class the smallest lane count that still gives 2048 wavefronts, never more lanes than
+    // points beyond the smallest configuration.
+    const int max_rows = kPplOf[kNumPpl - 1];
+    const int row_limits[3] = {16, max_rows, max_rows};
     int best = -1;
-    for (int lc = 0; lc < kNumLaneCfg; ++lc) {
-        const int lanes = kLanesOf[lc];
-        if (forced_lanes && lanes != forced_lanes) continue;
-        const int rows = (n_points + lanes - 1) / lanes;
-        if (rows > kPplOf[kNumPpl - 1]) continue;
-        // never more lanes than points (beyond the smallest configuration)
-        if (!forced_lanes && best >= 0 && kLanesOf[best] >= n_points) break;
-        best = lc;
-        const int64_t waves = chains * lanes / 64;
-        if (waves >= 2048) break;
+    for (int cls = 0; cls < 3 && best < 0; ++cls) {
+        for (int lc = 0; lc < kNumLaneCfg; ++lc) {
+            const int lanes = kLanesOf[lc];
+            if (forced_lanes ? lanes != forced_lanes : ((cls < 2) != (lanes <= 64))) continue;
+            const int rows = (n_points + lanes - 1) / lanes;
+            if (rows > (forced_lanes ? max_rows : row_limits[cls])) continue;
+            if (!forced_lanes && best >= 0 && kLanesOf[best] >= n_points) break;
+            best = lc;
+            if (chains * lanes / 64 >= 2048) break;
+        }
     }
     if (best < 0) return t;  // the lane count cannot hold N points in the register budget
     const int lanes = kLanesOf[best];
