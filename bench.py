@@ -32,12 +32,17 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Per particle*point operation counts of the move kernel's inner loop (one
-# pseudo-Voigt profile evaluation and the Gaussian-noise residual per point per
-# proposal): t = x - mu, t^2, c t^2, s2 + t^2, aG e, fma(aL, l, .), r = D - g,
-# fma(r, r, acc) -> 8 VALU, plus exp2 and rcp -> 2 transcendental.
-VALU_PER_UNIT = {("pvoigt", "gauss"): 8, ("gauss", "gauss"): 6}
-TRANS_PER_UNIT = {("pvoigt", "gauss"): 2, ("gauss", "gauss"): 1}
+# Algorithmic work per particle*point of the move kernel, Gaussian noise.  A proposal of
+# a peak's centre or width re-evaluates its basis shapes at every point:
+#   pseudo-Voigt: t = x - mu, t^2, c t^2, s^2 + t^2, two fmas for the residual, one fma
+#   for r^2 -> 7 VALU, plus exp2 and rcp -> 2 transcendental;
+#   Gaussian peak: t, t^2, c t^2, one fma for the residual, one for r^2 -> 5 VALU + exp2.
+# A proposal of a linear coefficient (amplitude, Gaussian fraction, background) forms the
+# residual from cached shapes: counted as 2 VALU (one fma for the residual, one for r^2),
+# a lower bound.
+SHAPE_VALU = {"pvoigt": 7, "gauss": 5}
+SHAPE_TRANS = {"pvoigt": 2, "gauss": 1}
+LINEAR_VALU = 2
 # Issue cost of one transcendental relative to one VALU instruction on gfx950,
 # measured with a throughput microbenchmark (see the design notes).
 TRANS_COST = float(os.environ.get("SMC_TRANS_COST", "2.0"))
@@ -186,12 +191,15 @@ def main():
 
     prof0 = s.profile()
     evals, lat, logz, stages = 0, [], [], []
+    kinds = {"stage0": 0, "shape": 0, "linear": 0}
     t0 = time.perf_counter()
     for k in range(args.steps):
         ts = time.perf_counter()
         s.reset(k + 1)
         s.run()
         evals += s.evaluations()
+        for key, v in s.evaluation_kinds().items():
+            kinds[key] += v
         lat.append(time.perf_counter() - ts)
         logz.append(s.log_evidence())
         stages.append(max(s.stage_info(K)[0] for K in ks))
@@ -201,18 +209,21 @@ def main():
     elapsed = t1 - t0
     value = evals * spec.n / elapsed
 
-    # roofline of the dominant kernel (the MH move): algorithmic lane-instructions per launch
-    # over the launch's average duration from HIP events on the library's stream
-    move_evals = evals - args.steps * P * len(ks)
-    key = (spec.peak_kind, spec.noise_kind)
-    per_unit = VALU_PER_UNIT[key] + TRANS_COST * TRANS_PER_UNIT[key]
+    # roofline of the dominant kernel (the MH move): algorithmic lane-instruction slots per
+    # launch over the launch's average duration from HIP events on the library's stream
+    assert kinds["stage0"] + kinds["shape"] + kinds["linear"] == evals
+    shape_slots = SHAPE_VALU[spec.peak_kind] + TRANS_COST * SHAPE_TRANS[spec.peak_kind]
+    slots = (kinds["shape"] * shape_slots + kinds["linear"] * LINEAR_VALU) * spec.n
+    move_units = (kinds["shape"] + kinds["linear"]) * spec.n
     launches = prof1["move_launches"] - prof0["move_launches"]
     move_s = (prof1["move_ms"] - prof0["move_ms"]) / 1e3
-    achieved = move_evals * spec.n * per_unit / move_s
+    achieved = slots / move_s
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                 "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
                 "kernel": "k_move", "avg_launch_ms": move_s * 1e3 / max(launches, 1),
-                "ops_per_unit": per_unit, "units_per_launch": move_evals * spec.n / max(launches, 1)}
+                "ops_per_unit": slots / max(move_units, 1), "units_per_launch": move_units / max(launches, 1),
+                "shape_evals": kinds["shape"], "linear_evals": kinds["linear"],
+                "slots_shape": shape_slots, "slots_linear": LINEAR_VALU}
 
     out = {
         "metric": "particle*point likelihood evals/s",

@@ -132,6 +132,12 @@ smc_status smc_reset(smc_ctx* ctx, uint64_t seed);
  * Metropolis proposal inside the prior's support.  Each evaluation covers all N points. */
 smc_status smc_evaluations(const smc_ctx* ctx, uint64_t* n_evals);
 
+/* The evaluations of smc_evaluations by kind, out (host) [3]: {stage-0 evaluations (every
+ * term evaluated), proposals that changed a peak's centre or width (its basis shapes
+ * re-evaluated at every point), proposals that changed a linear coefficient (amplitude,
+ * Gaussian fraction, background; residuals formed from cached shapes)}. */
+smc_status smc_evaluation_kinds(const smc_ctx* ctx, uint64_t* out);
+
 /* With options.profile = 1: out (host) [4] = {total ms of move launches, number of move
  * launches, total ms of stage launches, number of stage launches}, measured with HIP events
  * on the context's stream. */

@@ -13,24 +13,21 @@
 // (one peak, or the background), so every lane keeps, per point,
 //   D = y - (model without the current term)   (Gaussian noise)
 //   D = model without the current term          (Poisson counts)
-// and G = the current term's value.  A proposal then costs one profile
-// evaluation per point; moving to the next term costs one more.  D and G are
-// rebuilt from scratch every few sweeps, so rounding cannot accumulate.
+// and the current peak's basis shapes at every point, t = x - mu: e = exp(-(b/2) t^2)
+// for a Gaussian peak (value A e); e = exp(-ln2 t^2 / s^2) and l = 1 / (s^2 + t^2)
+// for a pseudo-Voigt peak (value A eta e + A (1 - eta) s^2 l).  The background
+// c0 + c1 x needs no cache.  Each term is linear in its remaining parameters, so a
+// proposal of a
+// centre or width re-evaluates the shapes (the transcendental work); a proposal
+// of an amplitude, a Gaussian fraction or a background coefficient only forms
+// the residual from the cached shapes.  Moving to the next term costs one
+// shape evaluation.  D and the shapes are rebuilt from scratch every few
+// sweeps, so rounding cannot accumulate.
 #pragma once
 
 #include "smc_device.hpp"
 
 namespace smc {
-
-template <int NZ>
-__device__ __forceinline__ float point_term(float D, float g, float y) {
-    if constexpr (NZ == SMC_NOISE_GAUSS) {
-        const float r = D - g;
-        return r * r;
-    } else {
-        return poisson_dev(y, D + g);
-    }
-}
 
 // Points beyond N (the tile holds LC * PPL >= N) are loaded with x = kFarX,
 // where every peak profile underflows to 0 and the background is masked, and
@@ -38,19 +35,28 @@ __device__ __forceinline__ float point_term(float D, float g, float y) {
 // to 0): they contribute exactly 0, so the point loops need no bounds.
 constexpr float kFarX = 1.0e18f;
 
-// The residual cache D, G is rebuilt from the parameters every kRebuildEvery
-// sweeps (and at every chain start), which bounds the rounding it accumulates
-// through term-to-term updates to a few sweeps.
+// The residual cache D and the shapes are rebuilt from the parameters every
+// kRebuildEvery sweeps (and at every chain start), which bounds the rounding
+// they accumulate through term-to-term updates to a few sweeps.
 constexpr int kRebuildEvery = 4;
+
+// Component q of a peak enters its term linearly: amplitude (both kinds) and
+// Gaussian fraction (pseudo-Voigt).
+template <int PK>
+__device__ __forceinline__ bool linear_component(int q) {
+    return q == 0 || (PK == SMC_PEAK_PVOIGT && q == 3);
+}
 
 template <int PK, int NZ, int L, int WPC, int PPL>
 struct ChainState {
     static constexpr int LC = L * WPC;
+    static constexpr bool kPV = PK == SMC_PEAK_PVOIGT;
+    static constexpr bool kGaussNoise = NZ == SMC_NOISE_GAUSS;
     float x[PPL];
-    float y[NZ == SMC_NOISE_POISSON ? PPL : 1];
+    float y[kGaussNoise ? 1 : PPL];
     float D[PPL];
-    float G[PPL];
-    float Gn[PPL];
+    float S1[PPL];
+    float S2[kPV ? PPL : 1];
 
     __device__ __forceinline__ void load_points(const GroupDesc& g, int lane) {
 #pragma unroll
@@ -58,7 +64,7 @@ struct ChainState {
             const int i = lane + p * LC;
             const bool ok = i < g.n;
             x[p] = ok ? g.x[i] : kFarX;
-            if constexpr (NZ == SMC_NOISE_POISSON) y[p] = ok ? g.y[i] : -1.0f;
+            if constexpr (!kGaussNoise) y[p] = ok ? g.y[i] : -1.0f;
         }
     }
 
@@ -67,28 +73,121 @@ struct ChainState {
         return k < g.K ? peak_consts<PK>(th + k * g.np) : bg_consts(th + g.K * g.np, g.nbg);
     }
 
-    __device__ __forceinline__ void eval_term(bool is_bg, const PeakC& q, float* out) const {
-        if (is_bg) {
-#pragma unroll
-            for (int p = 0; p < PPL; ++p) out[p] = x[p] < 1.0e17f ? bg_eval(x[p], q) : 0.0f;
-        } else {
-#pragma unroll
-            for (int p = 0; p < PPL; ++p) out[p] = peak_eval<PK>(x[p], q);
-        }
+    // Unit shapes of a peak at point p.
+    __device__ __forceinline__ void shape_at(const PeakC& q, int p, float& e, float& l) const {
+        const float t = x[p] - q.mu;
+        const float t2 = t * t;
+        e = __builtin_amdgcn_exp2f(q.c * t2);
+        if constexpr (kPV) l = __builtin_amdgcn_rcpf(q.s2 + t2);
+        else l = 0.0f;
     }
 
-    // Sum of the per-point energy terms with the current term's values `gv`.
-    __device__ __forceinline__ float partial(const float* gv) const {
+    __device__ __forceinline__ float s2(int p) const {
+        if constexpr (kPV) return S2[p];
+        else return 0.0f;
+    }
+
+    // D + sg * (value of the peak with shapes e, l): sg = -1 takes the term out of the
+    // Gaussian residual, +1 adds it to the Poisson model.
+    __device__ __forceinline__ static float add_peak(float Dp, float sg, const PeakC& q, float e, float l) {
+        float r = __builtin_fmaf(sg * q.aG, e, Dp);
+        if constexpr (kPV) r = __builtin_fmaf(sg * q.aL, l, r);
+        return r;
+    }
+
+    __device__ __forceinline__ float bg_at(const PeakC& q, int p) const {
+        return x[p] < 1.0e17f ? bg_eval(x[p], q) : 0.0f;
+    }
+
+    // Energy term of point p given the residual r (Gaussian) or the model value f (Poisson).
+    __device__ __forceinline__ float point_term(float rf, int p) const {
+        if constexpr (kGaussNoise) return rf * rf;
+        else return poisson_dev(y[p], rf);
+    }
+
+    static constexpr float kInclude = kGaussNoise ? -1.0f : 1.0f;
+
+    // Energy share of the current term with constants q (its shapes cached): the current
+    // state, or a proposal of a linear component of the current peak.
+    __device__ __forceinline__ float partial_linear(const PeakC& q) const {
         float acc = 0.0f;
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) acc += point_term<NZ>(D[p], gv[p], NZ == SMC_NOISE_POISSON ? y[p] : 0.0f);
+        for (int p = 0; p < PPL; ++p) acc += point_term(add_peak(D[p], kInclude, q, S1[p], s2(p)), p);
         return acc;
     }
 
-    // Rebuild D and G (current term = term 0) from th; returns this lane's share of the energy.
+    // Energy share of a proposal that changes the current peak's centre or width.
+    __device__ __forceinline__ float partial_shape(const PeakC& q) const {
+        float acc = 0.0f;
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            float e, l;
+            shape_at(q, p, e, l);
+            acc += point_term(add_peak(D[p], kInclude, q, e, l), p);
+        }
+        return acc;
+    }
+
+    // Energy share of a background proposal (the background is the current term).
+    __device__ __forceinline__ float partial_bg(const PeakC& q) const {
+        float acc = 0.0f;
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) acc += point_term(__builtin_fmaf(kInclude, bg_at(q, p), D[p]), p);
+        return acc;
+    }
+
+    // An accepted centre or width: the cached shapes follow the new constants.
+    __device__ __forceinline__ void accept_shape(const PeakC& q) {
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            float e, l;
+            shape_at(q, p, e, l);
+            S1[p] = e;
+            if constexpr (kPV) S2[p] = l;
+        }
+    }
+
+    // Term k with constants q joins the fixed part of the model held in D.
+    __device__ __forceinline__ void include(bool is_bg, const PeakC& q, bool cached) {
+        if (is_bg) {
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) D[p] = __builtin_fmaf(kInclude, bg_at(q, p), D[p]);
+        } else if (cached) {
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) D[p] = add_peak(D[p], kInclude, q, S1[p], s2(p));
+        } else {
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) {
+                float e, l;
+                shape_at(q, p, e, l);
+                D[p] = add_peak(D[p], kInclude, q, e, l);
+            }
+        }
+    }
+
+    // Term k with constants q leaves the fixed part and becomes the current term.  The
+    // background needs no shapes; clearing them there ends the previous peak's shapes on
+    // both paths, so they are not kept alive beside the new ones.
+    __device__ __forceinline__ void exclude(bool is_bg, const PeakC& q) {
+        if (is_bg) {
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) {
+                D[p] = __builtin_fmaf(-kInclude, bg_at(q, p), D[p]);
+                S1[p] = 0.0f;
+                if constexpr (kPV) S2[p] = 0.0f;
+            }
+        } else {
+            accept_shape(q);
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) D[p] = add_peak(D[p], -kInclude, q, S1[p], s2(p));
+        }
+    }
+
+    // Rebuild D and the shapes (current term = peak 0) from th; returns this lane's share of
+    // the energy.
     __device__ __forceinline__ float rebuild(const GroupDesc& g, const float* th, int lane) {
         const int kt = g.K + (g.nbg > 0 ? 1 : 0);
-        if constexpr (NZ == SMC_NOISE_GAUSS) {
+        if constexpr (kGaussNoise) {
 #pragma unroll
             for (int p = 0; p < PPL; ++p) {
                 const int i = lane + p * LC;
@@ -98,32 +197,16 @@ struct ChainState {
 #pragma unroll
             for (int p = 0; p < PPL; ++p) D[p] = 0.0f;
         }
-        for (int k = kt - 1; k >= 1; --k) {
-            eval_term(k == g.K, term_consts(g, th, k), Gn);
-#pragma unroll
-            for (int p = 0; p < PPL; ++p) {
-                if constexpr (NZ == SMC_NOISE_GAUSS) D[p] -= Gn[p];
-                else D[p] += Gn[p];
-            }
-        }
-        eval_term(0 == g.K, term_consts(g, th, 0), G);
-        return partial(G);
+        for (int k = kt - 1; k >= 1; --k) include(k == g.K, term_consts(g, th, k), false);
+        const PeakC q0 = term_consts(g, th, 0);
+        accept_shape(q0);
+        return partial_linear(q0);
     }
 
-    // Make term k current: D absorbs the old term's values and releases the new one's.
-    __device__ __forceinline__ void advance(bool is_bg, const PeakC& q) {
-        eval_term(is_bg, q, Gn);
-#pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-            if constexpr (NZ == SMC_NOISE_GAUSS) D[p] = (D[p] - G[p]) + Gn[p];
-            else D[p] = (D[p] + G[p]) - Gn[p];
-            G[p] = Gn[p];
-        }
-    }
-
-    __device__ __forceinline__ void accept() {
-#pragma unroll
-        for (int p = 0; p < PPL; ++p) G[p] = Gn[p];
+    // The current term moves from term `from` to term `to`.
+    __device__ __forceinline__ void transition(const GroupDesc& g, const float* th, int from, int to) {
+        include(from == g.K, term_consts(g, th, from), true);
+        exclude(to == g.K, term_consts(g, th, to));
     }
 };
 
@@ -185,16 +268,22 @@ __global__ void __launch_bounds__(256) k_energy(const GroupDesc* __restrict__ gr
 // LDS per chain slot: theta[d], increment s_j z_j [d], ln u_j [d]; then the
 // per-component accept counters [d] and the cross-wave reduction buffer.
 // ---------------------------------------------------------------------------
-// Waves per SIMD the register allocator is asked to leave room for: the cached
-// point state grows with PPL (x, D, G, Gn per point, and y for Poisson counts);
-// these limits are the largest that compile without spilling on gfx950.
-constexpr int move_min_waves(int noise, int points) {
-    return noise == SMC_NOISE_GAUSS ? (points <= 12 ? 5 : (points <= 16 ? 4 : (points <= 20 ? 3 : 2)))
-                                    : (points <= 8 ? 5 : (points <= 12 ? 4 : (points <= 16 ? 3 : 2)));
+// Waves per SIMD the register allocator is asked to leave room for.  The cached
+// point state grows with PPL (x, D and the shapes: one for a Gaussian peak, two
+// for a pseudo-Voigt peak; y too and the deviance's temporaries for Poisson
+// counts); these limits are the largest that compile without spilling on gfx950
+// (pseudo-Voigt with Poisson counts at 32 points per lane spills a few words).
+constexpr int move_min_waves(int peak, int noise, int points) {
+    if (noise == SMC_NOISE_GAUSS) {
+        if (peak == SMC_PEAK_GAUSS) return points <= 16 ? 5 : (points <= 20 ? 4 : (points <= 24 ? 3 : 2));
+        return points <= 10 ? 5 : (points <= 16 ? 4 : (points <= 20 ? 3 : 2));
+    }
+    if (peak == SMC_PEAK_GAUSS) return points <= 8 ? 5 : (points <= 14 ? 4 : (points <= 20 ? 3 : 2));
+    return points <= 7 ? 5 : (points <= 12 ? 4 : (points <= 16 ? 3 : 2));
 }
 
 template <int PK, int NZ, int L, int WPC, int PPL>
-__global__ void __launch_bounds__(256, move_min_waves(NZ, PPL)) k_move(const GroupDesc* __restrict__ groups,
+__global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL)) k_move(const GroupDesc* __restrict__ groups,
                                               const MoveWork* __restrict__ work) {
     using CS = ChainState<PK, NZ, L, WPC, PPL>;
     constexpr int LC = CS::LC;
@@ -213,7 +302,7 @@ __global__ void __launch_bounds__(256, move_min_waves(NZ, PPL)) k_move(const Gro
     float* lnu = inc + d;
     uint32_t* accc = reinterpret_cast<uint32_t*>(lds + CPW * 3 * d);
     float* red = lds + CPW * 3 * d + d;
-    uint32_t* nevals = reinterpret_cast<uint32_t*>(red + 2 * WPC);
+    uint32_t* nevals = reinterpret_cast<uint32_t*>(red + 2 * WPC);   // [0] shape, [1] linear
 
     const bool active = slot < w.nchains;
     const int m = w.chain0 + slot;
@@ -223,8 +312,8 @@ __global__ void __launch_bounds__(256, move_min_waves(NZ, PPL)) k_move(const Gro
     const uint32_t K = static_cast<uint32_t>(g.K);
 
     for (int j = threadIdx.x; j < d; j += 256) accc[j] = 0u;
-    if (threadIdx.x == 0) *nevals = 0u;
-    uint32_t my_evals = 0;
+    if (threadIdx.x < 2) nevals[threadIdx.x] = 0u;
+    uint32_t my_shape = 0, my_linear = 0;
     float E = 0.0f;
     if (active) {
         for (int j = lane; j < d; j += LC) th[j] = g.start[(size_t)j * g.M + m];
@@ -250,13 +339,13 @@ __global__ void __launch_bounds__(256, move_min_waves(NZ, PPL)) k_move(const Gro
                 E = chain_sum<L, WPC>(cs.rebuild(g, th, lane), red, parity);
                 if (NZ == SMC_NOISE_GAUSS) E *= g.inv2s2;
             } else if (kt > 1) {
-                cs.advance(0 == g.K, CS::term_consts(g, th, 0));
+                cs.transition(g, th, kt - 1, 0);
             }
             for (int k = 0; k < kt; ++k) {
                 const bool is_bg = k == g.K;
                 const int j0 = is_bg ? g.K * g.np : k * g.np;
                 const int nq = is_bg ? g.nbg : g.np;
-                if (k > 0) cs.advance(is_bg, CS::term_consts(g, th, k));
+                if (k > 0) cs.transition(g, th, k - 1, k);
                 for (int q = 0; q < nq; ++q) {
                     const int j = j0 + q;
                     const DevPrior pr = g.prior[j];
@@ -273,14 +362,23 @@ __global__ void __launch_bounds__(256, move_min_waves(NZ, PPL)) k_move(const Gro
                     for (int u = 0; u < 4; ++u)
                         if (u == q) tmp[u] = vn;
                     const PeakC qn = is_bg ? bg_consts(tmp, g.nbg) : peak_consts<PK>(tmp);
-                    ++my_evals;
-                    cs.eval_term(is_bg, qn, cs.Gn);
-                    float En = chain_sum<L, WPC>(cs.partial(cs.Gn), red, parity);
+                    const bool linear = is_bg || linear_component<PK>(q);
+                    float part;
+                    if (is_bg) {
+                        part = cs.partial_bg(qn);
+                    } else if (linear) {
+                        part = cs.partial_linear(qn);
+                    } else {
+                        part = cs.partial_shape(qn);
+                    }
+                    if (linear) ++my_linear;
+                    else ++my_shape;
+                    float En = chain_sum<L, WPC>(part, red, parity);
                     if (NZ == SMC_NOISE_GAUSS) En *= g.inv2s2;
                     const float log_alpha = -beta * (En - E) + prior_log_ratio(pr, vn, vo);
                     if (lnu[j] < log_alpha) {
                         E = En;
-                        cs.accept();
+                        if (!linear) cs.accept_shape(qn);
                         th[j] = vn;
                         if (lane == 0) atomicAdd(&accc[j], 1u);
                     }
@@ -293,11 +391,17 @@ __global__ void __launch_bounds__(256, move_min_waves(NZ, PPL)) k_move(const Gro
             }
         }
     }
-    if (active && lane == 0 && my_evals) atomicAdd(nevals, my_evals);
+    if (active && lane == 0) {
+        if (my_shape) atomicAdd(&nevals[0], my_shape);
+        if (my_linear) atomicAdd(&nevals[1], my_linear);
+    }
     __syncthreads();
     for (int j = threadIdx.x; j < d; j += 256)
         if (accc[j]) atomicAdd(&g.acc[j], accc[j]);
-    if (threadIdx.x == 0 && *nevals) atomicAdd(&g.st->evals, static_cast<unsigned long long>(*nevals));
+    if (threadIdx.x == 0 && (nevals[0] | nevals[1])) {
+        atomicAdd(&g.st->evals, static_cast<unsigned long long>(nevals[0]) + nevals[1]);
+        if (nevals[1]) atomicAdd(&g.st->evals_linear, static_cast<unsigned long long>(nevals[1]));
+    }
 }
 
 }  // namespace smc

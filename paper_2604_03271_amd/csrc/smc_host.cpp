@@ -531,6 +531,19 @@ extern "C" smc_status smc_evaluations(const smc_ctx* c, uint64_t* n) {
     return SMC_OK;
 }
 
+extern "C" smc_status smc_evaluation_kinds(const smc_ctx* c, uint64_t* out) {
+    if (!c || !out) return SMC_EINVAL;
+    uint64_t all = 0, linear = 0;
+    for (const GroupState& s : c->states) {
+        all += s.evals;
+        linear += s.evals_linear;
+    }
+    out[0] = c->stage0_evals;
+    out[1] = all - linear;
+    out[2] = linear;
+    return SMC_OK;
+}
+
 extern "C" smc_status smc_profile(const smc_ctx* c, double* out) {
     if (!c || !out) return SMC_EINVAL;
     if (!c->opt.profile) return SMC_ESTATE;

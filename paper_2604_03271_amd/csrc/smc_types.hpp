@@ -31,7 +31,8 @@ struct GroupState {
     int32_t done;     // 1 once the final move at beta = 1 has run
     int32_t status;   // SMC_OK or SMC_ENUMERIC
     int32_t pad;
-    unsigned long long evals;  // likelihood evaluations of Metropolis proposals
+    unsigned long long evals;         // likelihood evaluations of Metropolis proposals
+    unsigned long long evals_linear;  // of which a linear coefficient changed (cached shapes)
 };
 
 constexpr int kTraceCols = 6;  // beta, delta, ess, lse, logz, acceptance

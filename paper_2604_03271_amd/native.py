@@ -94,6 +94,7 @@ _SIGNATURES = {
     "smc_reset": (c_i32, [c_vp, c_u64]),
     "smc_evaluations": (c_i32, [c_vp, P(c_u64)]),
     "smc_profile": (c_i32, [c_vp, P(c_d)]),
+    "smc_evaluation_kinds": (c_i32, [c_vp, P(c_u64)]),
     "smc_log_evidence": (c_i32, [c_vp, P(c_d), c_i32]),
     "smc_stage_info": (c_i32, [c_vp, c_i32, P(c_i32), P(c_d), P(c_d), P(c_d)]),
     "smc_trace": (c_i32, [c_vp, c_i32, P(c_d), P(c_d), P(c_d), P(c_d), c_i32, P(c_i32)]),
@@ -258,6 +259,12 @@ def smc_evaluations(ctx) -> int:
     return n.value
 
 
+def smc_evaluation_kinds(ctx) -> dict:
+    out = (c_u64 * 3)()
+    check(lib().smc_evaluation_kinds(ctx, out), "smc_evaluation_kinds")
+    return {"stage0": int(out[0]), "shape": int(out[1]), "linear": int(out[2])}
+
+
 def smc_profile(ctx) -> dict:
     out = np.zeros(4)
     check(lib().smc_profile(ctx, _pd(out)), "smc_profile")
@@ -352,6 +359,9 @@ class Sampler:
 
     def profile(self) -> dict:
         return smc_profile(self.ctx)
+
+    def evaluation_kinds(self) -> dict:
+        return smc_evaluation_kinds(self.ctx)
 
     def log_evidence(self, allow_partial=False) -> np.ndarray:
         return smc_log_evidence(self.ctx, self.k_max - self.k_min + 1, allow_partial)

@@ -231,3 +231,18 @@ def test_stage_matches_reference_at_full_size(orc, cfg, P, wf, n):
         # log Z after one stage = LSE - ln P (energies without the constant) - delta * C
         assert tr["logz"][0] == pytest.approx(lse_ref - math.log(P) - d_gpu * C, rel=1e-12, abs=1e-9)
     s.close()
+
+
+def test_evaluation_kinds():
+    """Evaluations split by kind add up; about half the pseudo-Voigt proposals are of linear
+    coefficients (A, eta of each peak, both background coefficients)."""
+    spec = W.config2(0)
+    say("evaluation kinds")
+    s = native.Sampler(spec, native.options(seed=3, n_particles=4096, n_moves=16, waste_free=True))
+    s.run()
+    k = s.evaluation_kinds()
+    assert k["stage0"] + k["shape"] + k["linear"] == s.evaluations()
+    assert k["stage0"] == 4096 * (spec.k_max - spec.k_min + 1)
+    frac = k["linear"] / (k["shape"] + k["linear"])
+    assert 0.3 < frac < 0.7, frac
+    s.close()
