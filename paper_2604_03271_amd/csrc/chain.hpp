@@ -239,7 +239,7 @@ __global__ void __launch_bounds__(256) k_energy(const GroupDesc* __restrict__ gr
                                                 const MoveWork* __restrict__ work) {
     using CS = ChainState<PK, NZ, L, WPC, PPL>;
     constexpr int LC = CS::LC;
-    const MoveWork w = work[blockIdx.x];
+    const MoveWork w = work[xcd_block(blockIdx.x, gridDim.x)];
     const GroupDesc& g = groups[w.group];
     extern __shared__ float lds[];
     const int slot = threadIdx.x / LC, lane = threadIdx.x % LC;
@@ -288,7 +288,7 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL)) k_move(const
     using CS = ChainState<PK, NZ, L, WPC, PPL>;
     constexpr int LC = CS::LC;
     constexpr int CPW = 256 / LC;
-    const MoveWork w = work[blockIdx.x];
+    const MoveWork w = work[xcd_block(blockIdx.x, gridDim.x)];
     const GroupDesc& g = groups[w.group];
     GroupState* st = g.st;
     if (st->done) return;

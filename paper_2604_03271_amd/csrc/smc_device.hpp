@@ -187,15 +187,36 @@ __device__ __forceinline__ float dpp_swap(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
 }
 
+// Across rows the gfx950 permlane swaps (VALU, no LDS round trip) return the even
+// and the odd row of each pair of rows (16 lanes), or the low and the high half of
+// the wavefront (32 lanes), in every lane; all lanes add them in the same order.
 template <int L>
 __device__ __forceinline__ float group_sum(float v) {
     v += dpp_swap<0xB1>(v);   // quad_perm [1,0,3,2]
     v += dpp_swap<0x4E>(v);   // quad_perm [2,3,0,1]
     v += dpp_swap<0x141>(v);  // row_half_mirror: quads of a half-row
     v += dpp_swap<0x140>(v);  // row_mirror: halves of a 16-lane row
-    if constexpr (L >= 32) v += __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), 0x401F));  // xor 16
-    if constexpr (L >= 64) v += __shfl_xor(v, 32, 64);
+    if constexpr (L >= 32) {
+        const auto p = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, v), __builtin_bit_cast(unsigned, v),
+                                                        false, false);
+        v = __builtin_bit_cast(float, p[0]) + __builtin_bit_cast(float, p[1]);
+    }
+    if constexpr (L >= 64) {
+        const auto p = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, v), __builtin_bit_cast(unsigned, v),
+                                                        false, false);
+        v = __builtin_bit_cast(float, p[0]) + __builtin_bit_cast(float, p[1]);
+    }
     return v;
+}
+
+// Logical block of block b in a launch of n blocks: consecutive workgroups go to the
+// 8 XCDs in turn, each with its own L2, so the logical order is re-dealt to give every
+// XCD one contiguous range of work items (neighbouring chains share cache lines of the
+// component-major particle arrays).  A bijection of [0, n).
+__device__ __forceinline__ int xcd_block(int b, int n) {
+    constexpr int kXcds = 8;
+    const int q = n / kXcds, rem = n % kXcds, x = b % kXcds, r = b / kXcds;
+    return x < rem ? x * (q + 1) + r : rem * (q + 1) + (x - rem) * q + r;
 }
 
 }  // namespace smc
