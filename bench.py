@@ -50,30 +50,67 @@ TRANS_COST = float(os.environ.get("SMC_TRANS_COST", "2.0"))
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
 
-def cpu_baseline(spec, K, seconds_target=12.0):
-    """The FP64 reference's move (its hot loop) on a bounded sample of the same workload."""
-    import oracle
-    opr = oracle.Problem(spec)
-    threads = oracle.num_threads()
-    M = 8 * threads
-    n = 16
+# HBM bytes per launch of the move kernel from the committed rocprofv3 counter summary of the
+# bench workload (FETCH_SIZE and WRITE_SIZE runs, calibrated with a copy of known size), used
+# only while the move-kernel sources still hash to the value recorded with the counters.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "xps_pv_hbm_traffic.md")
+
+
+def recorded_traffic():
+    import hashlib
+    try:
+        fields = dict(line.split(" = ", 1) for line in open(TRAFFIC_FILE).read().splitlines() if " = " in line)
+        h = hashlib.sha256()
+        for f in fields["hashed_files"].split():
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest()[:16] != fields["source_sha256_16"].strip():
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _time_oracle_move(oracle, opr, spec, K, M, n):
     th, E = oracle.init(opr, K, M, seed=1, uid=spec.uid)
     step = 0.05 * th.std(axis=0)
     t0 = time.perf_counter()
     _, _, _, ne = oracle.move(opr, K, th, E, step, 1e-3, n, True, 1, spec.uid, 1, return_evals=True)
-    dt = time.perf_counter() - t0
-    # scale the sample to the target duration if it was too short
-    if dt < 0.25 * seconds_target:
-        reps = max(1, int(seconds_target / max(dt, 1e-3)) // 2)
-        M2 = min(M * reps, 64 * threads * 8)
-        th, E = oracle.init(opr, K, M2, seed=1, uid=spec.uid)
-        t0 = time.perf_counter()
-        _, _, _, ne = oracle.move(opr, K, th, E, step, 1e-3, n, True, 1, spec.uid, 1, return_evals=True)
-        dt = time.perf_counter() - t0
-        M = M2
+    return ne, time.perf_counter() - t0
+
+
+def cpu_baseline(spec, K, seconds_target=10.0):
+    """The FP64 reference's move (its hot loop) on bounded samples of the same workload, on all
+    host threads and on one."""
+    import oracle
+    opr = oracle.Problem(spec)
+    threads = oracle.num_threads()
+    n = 16
+    M = 8 * threads
+    ne, dt = _time_oracle_move(oracle, opr, spec, K, M, n)
+    if dt < 0.25 * seconds_target:   # scale the sample towards the target duration
+        M = min(M * max(1, int(seconds_target / max(dt, 1e-3)) // 2), 64 * threads * 8)
+        ne, dt = _time_oracle_move(oracle, opr, spec, K, M, n)
+    oracle.set_num_threads(1)
+    M1 = max(1, int(M * 0.5 * seconds_target / max(dt * threads, 1e-3)) // 1)
+    M1 = max(4, min(M1, M))
+    ne1, dt1 = _time_oracle_move(oracle, opr, spec, K, M1, n)
+    oracle.set_num_threads(threads)
     return {"value": ne * spec.n / dt, "unit": "particle*point evals/s", "cores": threads, "kind": "oracle",
+            "single_thread_value": ne1 * spec.n / dt1,
+            "host": {"cpu": _cpu_model(), "nproc": os.cpu_count()},
             "sample": f"reference MH move, K={K}, {M} chains x {n} waste-free sweeps at beta=1e-3, "
-                      f"{ne} likelihood evaluations of N={spec.n} points, {dt:.2f} s"}
+                      f"{ne} likelihood evaluations of N={spec.n} points, {dt:.2f} s on {threads} threads; "
+                      f"single thread: {M1} chains, {ne1} evaluations, {dt1:.2f} s"}
 
 
 def batched(native, workloads, n_spectra, P=8192, plain_sample=4):
@@ -218,8 +255,9 @@ def main():
     launches = prof1["move_launches"] - prof0["move_launches"]
     move_s = (prof1["move_ms"] - prof0["move_ms"]) / 1e3
     achieved = slots / move_s
+    traffic = recorded_traffic() if args.workload == "xps-pv" and P == 65536 else None
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
                 "kernel": "k_move", "avg_launch_ms": move_s * 1e3 / max(launches, 1),
                 "ops_per_unit": slots / max(move_units, 1), "units_per_launch": move_units / max(launches, 1),
                 "shape_evals": kinds["shape"], "linear_evals": kinds["linear"],

@@ -105,6 +105,7 @@ def lib():
             "or_resample": (None, [PD, I32, I32, U32, PI]),
             "or_move": (ctypes.c_int64, [PP, I32, I32, I32, I32, D, U64, U32, U32, PD, PD, PD, PD, PD, PI]),
             "or_num_threads": (I32, []),
+            "or_set_num_threads": (None, [I32]),
             "or_step_sizes": (None, [PD, I32, I32, PD, PD]),
             "or_update_lambda": (None, [PD, PI, I32, D]),
             "or_run": (I32, [PP, I32, ctypes.POINTER(_Options), ctypes.POINTER(_Result)]),
@@ -265,6 +266,10 @@ def update_lambda(lam, acc, proposals: float) -> np.ndarray:
     acc = np.ascontiguousarray(acc, dtype=np.int32)
     lib().or_update_lambda(_pd(lam), acc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(lam), float(proposals))
     return lam
+
+
+def set_num_threads(n: int) -> None:
+    lib().or_set_num_threads(n)
 
 
 def num_threads() -> int:

@@ -426,6 +426,16 @@ int or_num_threads(void)
 #endif
 }
 
+/* Thread count of later parallel loops (timing only; results do not depend on it). */
+void or_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Step sizes (Sec. II.B.4, rule of the design notes): s_j = lambda_j sd_j with
  * sd_j the population standard deviation of component j over the M resampled
  * states, floored at 1e-12 (|mean| + 1). */

@@ -69,6 +69,7 @@ int64_t or_move(const or_problem* p, int K, int M, int n, int waste_free, double
                 uint64_t seed, uint32_t uid, uint32_t stage, const double* step,
                 const double* start, const double* start_E, double* out, double* out_E, int32_t* acc);
 int or_num_threads(void);
+void or_set_num_threads(int n);
 void or_step_sizes(const double* theta, int M, int d, const double* lambda, double* step);
 void or_update_lambda(double* lambda, const int32_t* acc, int d, double proposals);
 int or_run(const or_problem* p, int K, const or_options* o, or_result* res);
