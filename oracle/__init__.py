@@ -21,8 +21,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 PEAK = {"gauss": 0, "pvoigt": 1}
-BG = {"none": 0, "const": 1, "linear": 2}
-NOISE = {"gauss": 0, "poisson": 1}
+BG = {"none": 0, "const": 1, "linear": 2, "shirley": 3}
+NOISE = {"gauss": 0, "poisson": 1, "hetero": 2}
 PRIOR = {"uniform": 0, "gamma": 1, "normal": 2, "fixed": 3}
 
 
@@ -42,6 +42,7 @@ class _Problem(ctypes.Structure):
         ("peak_prior", _Prior * 4),
         ("bg_prior", _Prior * 2),
         ("peak_prior_k", ctypes.POINTER(_Prior)),
+        ("noise_s", ctypes.c_double * 3),
     ]
 
 
@@ -95,6 +96,9 @@ def lib():
             "or_peak_gauss": (D, [D, D, D, D]),
             "or_peak_pv": (D, [D, D, D, D, D]),
             "or_forward": (D, [PP, I32, PD, D]),
+            "or_peaks": (D, [PP, I32, PD, D]),
+            "or_shirley": (None, [PD, PD, I32, D, D, PD]),
+            "or_model": (None, [PP, I32, PD, PD]),
             "or_energy": (D, [PP, I32, PD]),
             "or_prior_in_support": (I32, [_Prior, D]),
             "or_prior_logpdf": (D, [_Prior, D]),
@@ -159,6 +163,9 @@ class Problem:
                 rows.extend(_prior(p) for p in rr)
             self._pk = (_Prior * len(rows))(*rows)
             pr.peak_prior_k = ctypes.cast(self._pk, ctypes.POINTER(_Prior))
+        ns = getattr(spec, "noise_s", None) or (0.0, 0.0, 0.0)
+        for q in range(3):
+            pr.noise_s[q] = float(ns[q])
         self.c = pr
 
     @property
@@ -200,6 +207,22 @@ def peak_pv(x, A, mu, sigma, eta) -> float:
 def forward(prob: Problem, K: int, theta, x: float) -> float:
     th = np.ascontiguousarray(theta, dtype=np.float64)
     return lib().or_forward(prob.ref, K, _pd(th), float(x))
+
+
+def model(prob: Problem, K: int, theta) -> np.ndarray:
+    """The forward model at every data point (any background, Shirley included)."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    f = np.zeros(len(prob.x))
+    lib().or_model(prob.ref, K, _pd(th), _pd(f))
+    return f
+
+
+def shirley(x, peaks, a: float, b: float) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    pk = np.ascontiguousarray(peaks, dtype=np.float64)
+    out = np.zeros(len(x))
+    lib().or_shirley(_pd(x), _pd(pk), len(x), float(a), float(b), _pd(out))
+    return out
 
 
 def energy(prob: Problem, K: int, theta) -> float:

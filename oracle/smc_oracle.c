@@ -105,6 +105,8 @@ double or_box_muller(uint32_t r0, uint32_t r1)
  * ------------------------------------------------------------------------ */
 int or_params_per_peak(int peak_kind) { return peak_kind == OR_PEAK_GAUSS ? 3 : 4; }
 int or_params_bg(int bg_kind) { return bg_kind == OR_BG_NONE ? 0 : (bg_kind == OR_BG_CONST ? 1 : 2); }
+/* (The Shirley background of App. D has two parameters too: the intensities a at the first
+ * and b at the last data point.) */
 int or_dim(const or_problem* p, int K) { return K * or_params_per_peak(p->peak_kind) + or_params_bg(p->bg_kind); }
 
 /* Prior of component j for a model with K peaks. */
@@ -137,8 +139,8 @@ double or_peak_pv(double x, double A, double mu, double sigma, double eta)
     return A * (eta * gauss + (1.0 - eta) * lorentz);
 }
 
-/* Forward model, Eq. (forward_model): sum of K basis functions plus baseline. */
-double or_forward(const or_problem* p, int K, const double* theta, double x)
+/* Sum of the K basis functions at x. */
+double or_peaks(const or_problem* p, int K, const double* theta, double x)
 {
     int np = or_params_per_peak(p->peak_kind);
     double f = 0.0;
@@ -147,21 +149,104 @@ double or_forward(const or_problem* p, int K, const double* theta, double x)
         if (p->peak_kind == OR_PEAK_GAUSS) f += or_peak_gauss(x, t[0], t[1], t[2]);
         else f += or_peak_pv(x, t[0], t[1], t[2], t[3]);
     }
-    const double* bg = theta + K * np;
+    return f;
+}
+
+/* Forward model, Eq. (forward_model): sum of K basis functions plus a pointwise baseline
+ * (none, constant, linear).  The Shirley baseline depends on the whole grid: or_model. */
+double or_forward(const or_problem* p, int K, const double* theta, double x)
+{
+    double f = or_peaks(p, K, theta, x);
+    const double* bg = theta + K * or_params_per_peak(p->peak_kind);
     if (p->bg_kind == OR_BG_CONST) f += bg[0];
     else if (p->bg_kind == OR_BG_LINEAR) f += bg[0] + bg[1] * x;
+    else if (p->bg_kind == OR_BG_SHIRLEY) f = NAN;
     return f;
+}
+
+/* Dynamic Shirley background (App. D, after Shirley 1972 and Herrera-Gomez 2014): the
+ * inelastic background at a point is proportional to the peak intensity integrated from
+ * the first data point up to it, scaled so that it equals a at the first point and b at the
+ * last:  B_i = a + (b - a) C_i / C_n,  C_1 = 0,
+ *        C_i = C_{i-1} + (x_i - x_{i-1}) (peaks_{i-1} + peaks_i) / 2   (trapezoid rule),
+ * with peaks the model's peak sum (the "dynamic" form: the fitted peaks, not the data).
+ * With no peak area (C_n = 0) the limit of a flat peak sum is used: C_i / C_n = (x_i - x_1) /
+ * (x_n - x_1).  x must increase. */
+void or_shirley(const double* x, const double* peaks, int n, double a, double b, double* B)
+{
+    double C = 0.0;
+    B[0] = 0.0;
+    for (int i = 1; i < n; ++i) {
+        C += (x[i] - x[i - 1]) * 0.5 * (peaks[i - 1] + peaks[i]);
+        B[i] = C;
+    }
+    for (int i = 0; i < n; ++i) {
+        double u = C > 0.0 ? B[i] / C : (n > 1 ? (x[i] - x[0]) / (x[n - 1] - x[0]) : 0.0);
+        B[i] = a + (b - a) * u;
+    }
+}
+
+/* The forward model at every data point into f [n]. */
+void or_model(const or_problem* p, int K, const double* theta, double* f)
+{
+    if (p->bg_kind != OR_BG_SHIRLEY) {
+        for (int i = 0; i < p->n; ++i) f[i] = or_forward(p, K, theta, p->x[i]);
+        return;
+    }
+    double* peaks = (double*)malloc(sizeof(double) * (size_t)p->n);
+    for (int i = 0; i < p->n; ++i) peaks[i] = or_peaks(p, K, theta, p->x[i]);
+    const double* bg = theta + K * or_params_per_peak(p->peak_kind);
+    or_shirley(p->x, peaks, p->n, bg[0], bg[1], f);
+    for (int i = 0; i < p->n; ++i) f[i] += peaks[i];
+    free(peaks);
 }
 
 /* Energy = negative log-likelihood -ln p(D|theta), with every constant kept.
  *   Gaussian noise (App. B, sigma known):  (N/2) ln(2 pi sigma^2) + sum (y-f)^2 / (2 sigma^2)
  *   Poisson counts (Eq. (xrd_poisson)):     sum [ f - y ln f + ln y! ],  +inf if some f <= 0
- * The paper writes both energies divided by N; the tempered likelihood p(D|theta)^beta
+ *   heteroscedastic Gaussian noise (App. D): sigma_i^2 = s0^2 f_i + s1^2 f_i^2 + s2^2 and
+ *     sum [ (1/2) ln(2 pi sigma_i^2) + (y_i - f_i)^2 / (2 sigma_i^2) ],  +inf if some
+ *     sigma_i^2 <= 0 (the printed form lacks the 1/2 of the quadratic term; the Gaussian
+ *     negative log-likelihood has it)
+ * The paper writes the energies divided by N; the tempered likelihood p(D|theta)^beta
  * uses the undivided form. */
+static double energy_hetero(const or_problem* p, const double* f)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    const double a = p->noise_s[0] * p->noise_s[0], b = p->noise_s[1] * p->noise_s[1],
+                 c = p->noise_s[2] * p->noise_s[2];
+    double e = 0.0;
+    for (int i = 0; i < p->n; ++i) {
+        double s2 = a * f[i] + b * f[i] * f[i] + c;
+        if (!(s2 > 0.0) || !isfinite(s2)) return INFINITY;
+        double r = p->y[i] - f[i];
+        e += 0.5 * log(two_pi * s2) + r * r / (2.0 * s2);
+    }
+    return e;
+}
+
 double or_energy(const or_problem* p, int K, const double* theta)
 {
     const double two_pi = 6.283185307179586476925286766559;
     double e = 0.0;
+    if (p->noise_kind == OR_NOISE_HETERO || p->bg_kind == OR_BG_SHIRLEY) {
+        double* f = (double*)malloc(sizeof(double) * (size_t)p->n);
+        or_model(p, K, theta, f);
+        if (p->noise_kind == OR_NOISE_HETERO) {
+            e = energy_hetero(p, f);
+        } else if (p->noise_kind == OR_NOISE_GAUSS) {
+            double s2 = p->sigma * p->sigma;
+            for (int i = 0; i < p->n; ++i) e += (p->y[i] - f[i]) * (p->y[i] - f[i]) / (2.0 * s2);
+            e += 0.5 * (double)p->n * log(two_pi * s2);
+        } else {
+            for (int i = 0; i < p->n && isfinite(e); ++i) {
+                if (!(f[i] > 0.0)) e = INFINITY;
+                else e += f[i] - p->y[i] * log(f[i]) + lgamma(p->y[i] + 1.0);
+            }
+        }
+        free(f);
+        return e;
+    }
     if (p->noise_kind == OR_NOISE_GAUSS) {
         double s2 = p->sigma * p->sigma;
         for (int i = 0; i < p->n; ++i) {

@@ -8,8 +8,8 @@
 #include <stdint.h>
 
 enum { OR_PEAK_GAUSS = 0, OR_PEAK_PVOIGT = 1 };
-enum { OR_BG_NONE = 0, OR_BG_CONST = 1, OR_BG_LINEAR = 2 };
-enum { OR_NOISE_GAUSS = 0, OR_NOISE_POISSON = 1 };
+enum { OR_BG_NONE = 0, OR_BG_CONST = 1, OR_BG_LINEAR = 2, OR_BG_SHIRLEY = 3 };
+enum { OR_NOISE_GAUSS = 0, OR_NOISE_POISSON = 1, OR_NOISE_HETERO = 2 };
 enum { OR_PRIOR_UNIFORM = 0, OR_PRIOR_GAMMA = 1, OR_PRIOR_NORMAL = 2, OR_PRIOR_FIXED = 3 };
 
 /* Uniform(a=lo, b=hi) | Gamma(a=shape, b=rate) | Normal(a=mean, b=sd) | Fixed(a=value) */
@@ -27,6 +27,7 @@ typedef struct {
     or_prior peak_prior[4];
     or_prior bg_prior[2];
     const or_prior* peak_prior_k; /* optional [k][4] per-peak priors, NULL = peak_prior for all */
+    double noise_s[3];            /* heteroscedastic noise: sigma0, sigma1, sigma2 */
 } or_problem;
 
 typedef struct {
@@ -54,7 +55,10 @@ int or_dim(const or_problem* p, int K);
 or_prior or_component_prior(const or_problem* p, int K, int j);
 double or_peak_gauss(double x, double A, double mu, double b);
 double or_peak_pv(double x, double A, double mu, double sigma, double eta);
+double or_peaks(const or_problem* p, int K, const double* theta, double x);
 double or_forward(const or_problem* p, int K, const double* theta, double x);
+void or_shirley(const double* x, const double* peaks, int n, double a, double b, double* B);
+void or_model(const or_problem* p, int K, const double* theta, double* f);
 double or_energy(const or_problem* p, int K, const double* theta);
 
 int or_prior_in_support(or_prior pr, double v);

@@ -28,8 +28,8 @@ class Spectrum:
     x: np.ndarray
     y: np.ndarray
     peak_kind: str                    # "gauss" (A, mu, b=precision) | "pvoigt" (A, mu, sigma=HWHM, eta=Gaussian fraction)
-    bg_kind: str                      # "none" | "const" (b) | "linear" (c0, c1)
-    noise_kind: str                   # "gauss" (known sigma) | "poisson"
+    bg_kind: str                      # "none" | "const" (b) | "linear" (c0, c1) | "shirley" (a, b)
+    noise_kind: str                   # "gauss" (known sigma) | "poisson" | "hetero" (noise_s)
     sigma: float
     peak_prior: Sequence[Prior]
     bg_prior: Sequence[Prior]
@@ -38,6 +38,7 @@ class Spectrum:
     peak_prior_k: Optional[List[Sequence[Prior]]] = None
     truth: Optional[dict] = None
     uid: int = 0
+    noise_s: Optional[Tuple[float, float, float]] = None   # heteroscedastic noise (s0, s1, s2)
 
     @property
     def n(self) -> int:
@@ -262,3 +263,57 @@ def paper_gaussian(K: int, index: int = 0, k_span: int = 0) -> Spectrum:
     pri = [("gamma", 5.0, 5.0), mu_prior, ("gamma", 5.0, 0.04)]
     return Spectrum(x, y, "gauss", "none", "gauss", sigma, pri, [], max(1, K - k_span), K + k_span,
                     truth={"K": K, "peaks": peaks}, uid=6000 + 100 * K + index)
+
+
+# --- an XPS-like stand-in for the paper's Ni 2p HAXPES spectrum (Sec. III.B.2, App. D) -------
+# The measured spectrum is not available.  The stand-in keeps its shape: N = 840 points on a
+# binding-energy grid of about 845-887 eV, seven pseudo-Voigt peaks at the positions of table
+# xps_basis_assignment (main lines and satellites), a dynamic Shirley background and the
+# heteroscedastic noise sigma_i^2 = s0^2 f_i + s1^2 f_i^2 + s2^2 with (s0, s1, s2) =
+# (1, 0.01, 0).  Amplitudes, widths, mixing ratios and the background endpoints are drawn here.
+
+XPS_CENTRES = [851.65, 853.44, 858.83, 863.04, 869.07, 870.86, 877.02]
+XPS_MAIN = [True, True, False, False, True, True, False]
+XPS_NOISE = (1.0, 0.01, 0.0)
+
+
+def _gen_shirley(x, peaks_sum, a, b):
+    """Generating Shirley background: a + (b - a) * (trapezoid integral of the peak sum from the
+    first point) / (total integral)."""
+    inc = np.diff(x) * 0.5 * (peaks_sum[1:] + peaks_sum[:-1])
+    c = np.concatenate([[0.0], np.cumsum(inc)])
+    return a + (b - a) * c / c[-1]
+
+
+def xps_priors(x, y, k_max):
+    """Data-dependent uniform priors of table xps_priors."""
+    ymin, ymax = float(np.min(y)), float(np.max(y))
+    peak = [("uniform", max(0.0, 0.3 * ymin), 1.05 * ymax), ("uniform", float(x[0]), float(x[-1])),
+            ("uniform", 0.1, 15.0), ("uniform", 0.0, 1.0)]
+    bg = [("uniform", 0.95 * float(y[0]), 1.01 * float(y[0])), ("uniform", 0.95 * float(y[-1]), 1.01 * float(y[-1]))]
+    return peak, bg
+
+
+def xps_shirley(index: int = 0, n: int = 840, k_min: int = 6, k_max: int = 8) -> Spectrum:
+    """XPS-like spectrum (stand-in for the paper's HAXPES data): 7 pseudo-Voigt peaks on a dynamic
+    Shirley background with heteroscedastic noise; candidates K = 6..8 as in the paper."""
+    rng = np.random.default_rng(1000 * 7 + index)
+    x = f32(np.linspace(845.0, 887.0, n))
+    amax = 2.0e4
+    peaks = []
+    for mu, main in zip(XPS_CENTRES, XPS_MAIN):
+        A = amax * (rng.uniform(0.6, 1.0) if main else rng.uniform(0.15, 0.4))
+        s = rng.uniform(0.6, 1.2) if main else rng.uniform(1.5, 3.0)
+        eta = rng.uniform(0.2, 0.8)
+        peaks.append((A, mu, s, eta))
+    a, b = rng.uniform(4.0e3, 6.0e3), rng.uniform(1.0e4, 1.4e4)
+    psum = _synth(x, "pvoigt", peaks)
+    f = psum + _gen_shirley(x, psum, a, b)
+    s0, s1, s2 = XPS_NOISE
+    sd = np.sqrt(s0 ** 2 * f + s1 ** 2 * f ** 2 + s2 ** 2)
+    y = f32(f + sd * rng.standard_normal(n))
+    pp, bgp = xps_priors(x, y, k_max)
+    sp = Spectrum(x, y, "pvoigt", "shirley", "hetero", 0.0, pp, bgp, k_min, k_max,
+                  truth={"K": 7, "peaks": peaks, "bg": (a, b)}, uid=7000 + index)
+    sp.noise_s = XPS_NOISE
+    return sp
