@@ -43,6 +43,14 @@ sys.path.insert(0, ROOT)
 SHAPE_VALU = {"pvoigt": 7, "gauss": 5}
 SHAPE_TRANS = {"pvoigt": 2, "gauss": 1}
 LINEAR_VALU = 2
+# XPS model form (Shirley background, heteroscedastic noise), per point: a centre/width
+# proposal forms the new shapes (4 VALU + exp2, rcp), the new value (2), the change (1),
+# its trapezoid increment and prefix (2), the new background (2), the residual (2) and the
+# noise term f, sigma^2, r^2, r^2/sigma^2, ln sigma^2 sum (6 VALU + log2, rcp): 19 VALU +
+# 4 transcendental; a linear proposal skips the shapes: counted as 8 VALU + 2 transcendental
+# (a background proposal's cost, the cheapest kind), a lower bound.
+XPS_SHAPE = (19, 4)
+XPS_LINEAR = (8, 2)
 # Issue cost of one transcendental relative to one VALU instruction on gfx950,
 # measured with a throughput microbenchmark (see the design notes).
 TRANS_COST = float(os.environ.get("SMC_TRANS_COST", "2.0"))
@@ -177,6 +185,11 @@ def _workload(name, native_options, workloads, particles):
         P, n = particles or 65536, 16
         desc = (f"XPS-like spectrum N=1001, 5 pseudo-Voigt peaks + linear background, sigma=0.02, "
                 f"K=1..8, P={P} per K, waste-free n={n}")
+    elif name == "xps-shirley":
+        spec = workloads.xps_shirley(0)
+        P, n = particles or 2_000_000, 100
+        desc = (f"XPS-like stand-in N={spec.n}, pseudo-Voigt peaks on a dynamic Shirley background, "
+                f"heteroscedastic noise, K={spec.k_min}..{spec.k_max}, P={P} per K, waste-free n={n}")
     else:
         K = int(name.split("-k")[1])
         spec = workloads.paper_gaussian(K)
@@ -192,7 +205,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="xps-pv", choices=["xps-pv", "paper-k3", "paper-k10", "paper-k30"])
+    ap.add_argument("--workload", default="xps-pv",
+                    choices=["xps-pv", "paper-k3", "paper-k10", "paper-k30", "xps-shirley"])
     ap.add_argument("--particles", type=int, default=0, help="particles per K (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -249,8 +263,13 @@ def main():
     # roofline of the dominant kernel (the MH move): algorithmic lane-instruction slots per
     # launch over the launch's average duration from HIP events on the library's stream
     assert kinds["stage0"] + kinds["shape"] + kinds["linear"] == evals
-    shape_slots = SHAPE_VALU[spec.peak_kind] + TRANS_COST * SHAPE_TRANS[spec.peak_kind]
-    slots = (kinds["shape"] * shape_slots + kinds["linear"] * LINEAR_VALU) * spec.n
+    if spec.noise_kind == "hetero":
+        shape_slots = XPS_SHAPE[0] + TRANS_COST * XPS_SHAPE[1]
+        linear_slots = XPS_LINEAR[0] + TRANS_COST * XPS_LINEAR[1]
+    else:
+        shape_slots = SHAPE_VALU[spec.peak_kind] + TRANS_COST * SHAPE_TRANS[spec.peak_kind]
+        linear_slots = LINEAR_VALU
+    slots = (kinds["shape"] * shape_slots + kinds["linear"] * linear_slots) * spec.n
     move_units = (kinds["shape"] + kinds["linear"]) * spec.n
     launches = prof1["move_launches"] - prof0["move_launches"]
     move_s = (prof1["move_ms"] - prof0["move_ms"]) / 1e3
@@ -261,7 +280,7 @@ def main():
                 "kernel": "k_move", "avg_launch_ms": move_s * 1e3 / max(launches, 1),
                 "ops_per_unit": slots / max(move_units, 1), "units_per_launch": move_units / max(launches, 1),
                 "shape_evals": kinds["shape"], "linear_evals": kinds["linear"],
-                "slots_shape": shape_slots, "slots_linear": LINEAR_VALU}
+                "slots_shape": shape_slots, "slots_linear": linear_slots}
 
     out = {
         "metric": "particle*point likelihood evals/s",

@@ -63,8 +63,8 @@ typedef int32_t smc_status;
 #define SMC_EAGAIN (-7)   /* server queue full / nothing ready yet */
 
 enum { SMC_PEAK_GAUSS = 0, SMC_PEAK_PVOIGT = 1 };
-enum { SMC_BG_NONE = 0, SMC_BG_CONST = 1, SMC_BG_LINEAR = 2 };
-enum { SMC_NOISE_GAUSS = 0, SMC_NOISE_POISSON = 1 };
+enum { SMC_BG_NONE = 0, SMC_BG_CONST = 1, SMC_BG_LINEAR = 2, SMC_BG_SHIRLEY = 3 };
+enum { SMC_NOISE_GAUSS = 0, SMC_NOISE_POISSON = 1, SMC_NOISE_HETERO = 2 };
 enum { SMC_PRIOR_UNIFORM = 0, SMC_PRIOR_GAMMA = 1, SMC_PRIOR_NORMAL = 2, SMC_PRIOR_FIXED = 3 };
 
 /* Priors of the paper's tables (spectral_priors, xrd_priors, xps_priors):
@@ -75,7 +75,16 @@ typedef struct {
     double a, b;
 } smc_prior;
 
-/* One spectrum D = {x_i, y_i} and its model family (Sec. II.A). */
+/* One spectrum D = {x_i, y_i} and its model family (Sec. II.A).
+ * Peaks: Gaussian (A, mu, b = precision; Eq. spectral_forward_model) or pseudo-Voigt
+ * (A, mu, sigma = HWHM, eta = Gaussian fraction; Eq. xps_forward_model).  Backgrounds: none,
+ * constant (c), linear (c0 + c1 x), or the dynamic Shirley background of App. D (a, b): the
+ * trapezoid integral of the model's peak sum from the first point, scaled so that the
+ * background is a at the first and b at the last point (x must increase).  Noise: Gaussian
+ * with known sigma, Poisson counts (Eq. xrd_poisson), or heteroscedastic Gaussian with
+ * sigma_i^2 = s0^2 f_i + s1^2 f_i^2 + s2^2 (App. D).  The Shirley background and the
+ * heteroscedastic noise go together, with pseudo-Voigt peaks and N <= 1024 (the XPS model
+ * form of App. D); other combinations of these two are SMC_EINVAL. */
 typedef struct {
     int32_t n_points;            /* N >= 1 */
     const double* x;             /* (host) [N]; copied at init and rounded to FP32 */
@@ -89,6 +98,7 @@ typedef struct {
     const smc_prior* peak_prior_k; /* (host) optional [k_max][4] per-peak priors; NULL = peak_prior */
     int32_t k_min, k_max;        /* candidate peak counts, 1 <= k_min <= k_max */
     uint32_t uid;                /* identity of the spectrum; part of the random-number key */
+    double noise_s[3];           /* s0, s1, s2 >= 0 of the heteroscedastic noise (ignored otherwise) */
 } smc_problem;
 
 typedef struct {

@@ -284,7 +284,7 @@ hipError_t copy_states(const PoolView& view, const std::vector<Entry*>& entries,
 Tile entry_tile(const smc_problem& p, const smc_options& o) {
     const int M = o.waste_free ? o.n_particles / o.n_moves : o.n_particles;
     const int64_t chains = static_cast<int64_t>(p.k_max - p.k_min + 1) * M;
-    return choose_tile(p.n_points, chains, o.lanes_per_chain);
+    return choose_tile(p, chains, o.lanes_per_chain);
 }
 
 }  // namespace
@@ -299,7 +299,7 @@ extern "C" smc_status smc_batch_run(const smc_problem* probs, int32_t n, const s
     for (int i = 0; i < n; ++i) {
         const smc_status st = validate(&probs[i], opt);
         if (st != SMC_OK) return st;
-        if (!entry_tile(probs[i], *opt).valid) return SMC_EINVAL;
+        if (!tile_has_kernels(probs[i], entry_tile(probs[i], *opt))) return SMC_EINVAL;
     }
     if (!device_ok()) return SMC_EDEVICE;
 
@@ -611,7 +611,7 @@ extern "C" smc_status smc_server_submit(smc_server* sv, const smc_problem* prob,
     smc_status st = validate(prob, &o);
     if (st != SMC_OK) return st;
     if (prob->k_max - prob->k_min + 1 > 32) return SMC_EINVAL;
-    if (!entry_tile(*prob, o).valid) return SMC_EINVAL;
+    if (!tile_has_kernels(*prob, entry_tile(*prob, o))) return SMC_EINVAL;
     auto e = std::make_unique<Entry>();
     e->id = request_id;
     e->opt = o;

@@ -51,8 +51,8 @@ smc_status make_hook_group(HookGroup& h, const smc_problem* prob, int K, int P, 
     if (!device_ok()) return SMC_EDEVICE;
     h.sp.assign(p);
     h.sp.prob.k_min = h.sp.prob.k_max = K;
-    h.tile = choose_tile(p.n_points, chains, lanes);
-    if (!h.tile.valid) return SMC_EINVAL;
+    h.tile = choose_tile(p, chains, lanes);
+    if (!tile_has_kernels(p, h.tile)) return SMC_EINVAL;
 
     std::vector<MoveWork> work;
     build_work(std::vector<int>{0}, std::vector<int>{chains}, h.tile, work);
@@ -76,15 +76,7 @@ smc_status make_hook_group(HookGroup& h, const smc_problem* prob, int K, int P, 
     if (!h.d_group || !h.d_state || !h.d_work || !dx || !dy || !pri || !lam || !cdf || !trace) return SMC_ENOMEM;
 
     GroupDesc& g = h.g;
-    g.n = p.n_points;
-    g.K = K;
-    g.np = params_per_peak(p.peak_kind);
-    g.nbg = params_bg(p.bg_kind);
-    g.d = d;
-    g.peak_kind = p.peak_kind;
-    g.bg_kind = p.bg_kind;
-    g.noise_kind = p.noise_kind;
-    g.inv2s2 = p.noise_kind == SMC_NOISE_GAUSS ? static_cast<float>(1.0 / (2.0 * p.sigma * p.sigma)) : 0.0f;
+    model_consts(p, K, g);
     g.x = dx;
     g.y = dy;
     g.prior = pri;

@@ -12,6 +12,7 @@
 namespace smc {
 
 constexpr int kMaxK = 64;
+constexpr int kMaxXpsPoints = 1024;   // XPS model form: 64 lanes x 16 points
 
 struct Tile {
     int lc, pi, lanes, ppl;
@@ -53,7 +54,10 @@ smc_prior component_prior(const smc_problem& p, int K, int j);
 smc_status validate(const smc_problem* p, const smc_options* o);
 double energy_constant(const smc_problem& p);
 DevPrior dev_prior(const smc_prior& p);
-Tile choose_tile(int n_points, int64_t chains, int forced_lanes);
+bool xps_model(const smc_problem& p);
+void model_consts(const smc_problem& p, int K, GroupDesc& g);
+Tile choose_tile(const smc_problem& p, int64_t chains, int forced_lanes);
+bool tile_has_kernels(const smc_problem& p, const Tile& t);
 size_t move_lds_bytes(const Tile& t, int d);
 size_t energy_lds_bytes(const Tile& t, int d);
 void build_work(const std::vector<int>& groups, const std::vector<int>& chains_of, const Tile& t,

@@ -31,6 +31,7 @@ const KernelTable& kernels() {
         register_kernels_01(g_table);
         register_kernels_10(g_table);
         register_kernels_11(g_table);
+        register_kernels_xps(g_table);
     });
     return g_table;
 }
@@ -64,9 +65,23 @@ smc_status validate(const smc_problem* p, const smc_options* o) {
     if (!p || !o) return SMC_EINVAL;
     if (p->n_points < 1 || !p->x || !p->y) return SMC_EINVAL;
     if (p->peak_kind != SMC_PEAK_GAUSS && p->peak_kind != SMC_PEAK_PVOIGT) return SMC_EINVAL;
-    if (p->bg_kind < SMC_BG_NONE || p->bg_kind > SMC_BG_LINEAR) return SMC_EINVAL;
-    if (p->noise_kind != SMC_NOISE_GAUSS && p->noise_kind != SMC_NOISE_POISSON) return SMC_EINVAL;
+    if (p->bg_kind < SMC_BG_NONE || p->bg_kind > SMC_BG_SHIRLEY) return SMC_EINVAL;
+    if (p->noise_kind < SMC_NOISE_GAUSS || p->noise_kind > SMC_NOISE_HETERO) return SMC_EINVAL;
     if (p->noise_kind == SMC_NOISE_GAUSS && !(p->sigma > 0.0 && std::isfinite(p->sigma))) return SMC_EINVAL;
+    if (xps_model(*p)) {
+        // the XPS model form: pseudo-Voigt peaks, Shirley background, heteroscedastic noise
+        if (p->bg_kind != SMC_BG_SHIRLEY || p->noise_kind != SMC_NOISE_HETERO || p->peak_kind != SMC_PEAK_PVOIGT)
+            return SMC_EINVAL;
+        if (p->n_points < 2 || p->n_points > kMaxXpsPoints) return SMC_EINVAL;
+        for (int i = 1; i < p->n_points; ++i)
+            if (!(static_cast<float>(p->x[i]) > static_cast<float>(p->x[i - 1]))) return SMC_EINVAL;
+        double ssum = 0.0;
+        for (double v : p->noise_s) {
+            if (!(v >= 0.0 && std::isfinite(v))) return SMC_EINVAL;
+            ssum += v;
+        }
+        if (!(ssum > 0.0)) return SMC_EINVAL;
+    }
     if (p->k_min < 1 || p->k_min > p->k_max || p->k_max > kMaxK) return SMC_EINVAL;
     for (int i = 0; i < p->n_points; ++i) {
         if (!std::isfinite(p->x[i]) || !std::isfinite(p->y[i])) return SMC_EINVAL;
@@ -94,9 +109,12 @@ smc_status validate(const smc_problem* p, const smc_options* o) {
     return SMC_OK;
 }
 
+bool xps_model(const smc_problem& p) { return p.bg_kind == SMC_BG_SHIRLEY || p.noise_kind == SMC_NOISE_HETERO; }
+
 double energy_constant(const smc_problem& p) {
     if (p.noise_kind == SMC_NOISE_GAUSS)
         return 0.5 * p.n_points * std::log(2.0 * M_PI * p.sigma * p.sigma);
+    if (p.noise_kind == SMC_NOISE_HETERO) return 0.5 * p.n_points * std::log(2.0 * M_PI);
     double c = 0.0;
     for (int i = 0; i < p.n_points; ++i) {
         const double y = static_cast<float>(p.y[i]);
@@ -122,8 +140,27 @@ DevPrior dev_prior(const smc_prior& p) {
 // count of the launch): the smallest lane count whose points fit the register
 // budget (<= 32 points per lane) and that still gives >= 2 waves per SIMD
 // (2048 waves on 256 CUs); otherwise the largest lane count that fits.
-Tile choose_tile(int n_points, int64_t chains, int forced_lanes) {
+Tile choose_tile(const smc_problem& p, int64_t chains, int forced_lanes) {
+    const int n_points = p.n_points;
     Tile t{};
+    if (xps_model(p)) {
+        // one wavefront per chain group, at most 16 points per lane (the Shirley scan runs
+        // across the lanes of one wavefront)
+        int best = -1;
+        for (int lc = 0; lc < kNumLaneCfg; ++lc) {
+            const int lanes = kLanesOf[lc];
+            if (lanes > 64 || (forced_lanes && lanes != forced_lanes)) continue;
+            if ((n_points + lanes - 1) / lanes > 16) continue;
+            if (!forced_lanes && best >= 0 && kLanesOf[best] >= n_points) break;
+            best = lc;
+            if (chains * lanes / 64 >= 2048) break;
+        }
+        if (best < 0) return t;
+        const int rows = (n_points + kLanesOf[best] - 1) / kLanesOf[best];
+        int pi = 0;
+        while (kPplOf[pi] < rows) ++pi;
+        return Tile{best, pi, kLanesOf[best], kPplOf[pi], true};
+    }
     // Preference: chains inside one wavefront with at most 16 points per lane (the move
     // kernel keeps 4+ waves per SIMD there), then up to 32 points per lane (2-3 waves),
     // then four wavefronts per chain (a cross-wave LDS reduction per proposal).  Within a
@@ -154,6 +191,11 @@ Tile choose_tile(int n_points, int64_t chains, int forced_lanes) {
     t.ppl = kPplOf[pi];
     t.valid = true;
     return t;
+}
+
+bool tile_has_kernels(const smc_problem& p, const Tile& t) {
+    return t.valid && kernels().move[p.peak_kind][p.noise_kind][t.lc][t.pi] &&
+           kernels().energy[p.peak_kind][p.noise_kind][t.lc][t.pi];
 }
 
 size_t move_lds_bytes(const Tile& t, int d) {
@@ -290,6 +332,20 @@ size_t spectrum_bytes(const smc_problem& p, const smc_options& o) {
     return b;
 }
 
+void model_consts(const smc_problem& p, int K, GroupDesc& g) {
+    g.n = p.n_points;
+    g.K = K;
+    g.np = params_per_peak(p.peak_kind);
+    g.nbg = params_bg(p.bg_kind);
+    g.d = K * g.np + g.nbg;
+    g.peak_kind = p.peak_kind;
+    g.bg_kind = p.bg_kind;
+    g.noise_kind = p.noise_kind;
+    g.inv2s2 = p.noise_kind == SMC_NOISE_GAUSS ? static_cast<float>(1.0 / (2.0 * p.sigma * p.sigma)) : 0.0f;
+    for (int q = 0; q < 3; ++q)
+        g.hn[q] = p.noise_kind == SMC_NOISE_HETERO ? static_cast<float>(p.noise_s[q] * p.noise_s[q]) : 0.0f;
+}
+
 // Fill descriptors for K = k_min..k_max of one spectrum, carving buffers from `arena`.
 // Host-side prior tables are uploaded through `staging` (device pointer, host vector pairs).
 bool describe_spectrum(const Spectrum& sp, const smc_options& o, Arena& arena, GroupState* d_states_base,
@@ -304,15 +360,7 @@ bool describe_spectrum(const Spectrum& sp, const smc_options& o, Arena& arena, G
     int si = first_state;
     for (int K = p.k_min; K <= p.k_max; ++K, ++si) {
         GroupDesc g{};
-        g.n = p.n_points;
-        g.K = K;
-        g.np = params_per_peak(p.peak_kind);
-        g.nbg = params_bg(p.bg_kind);
-        g.d = K * g.np + g.nbg;
-        g.peak_kind = p.peak_kind;
-        g.bg_kind = p.bg_kind;
-        g.noise_kind = p.noise_kind;
-        g.inv2s2 = p.noise_kind == SMC_NOISE_GAUSS ? static_cast<float>(1.0 / (2.0 * p.sigma * p.sigma)) : 0.0f;
+        model_consts(p, K, g);
         g.x = dx;
         g.y = dy;
         g.P = P;
@@ -440,8 +488,8 @@ extern "C" smc_status smc_init(smc_ctx** out, const smc_problem* prob, const smc
     const int P = opt->n_particles, M = opt->waste_free ? P / opt->n_moves : P;
     // tiles: one tile for all groups of the spectrum (same N); work ordered heaviest K first
     const int64_t chains = static_cast<int64_t>(c->ng) * M;
-    c->tile = choose_tile(prob->n_points, chains, opt->lanes_per_chain);
-    if (!c->tile.valid) return ctx_fail(c, SMC_EINVAL);
+    c->tile = choose_tile(*prob, chains, opt->lanes_per_chain);
+    if (!tile_has_kernels(*prob, c->tile)) return ctx_fail(c, SMC_EINVAL);
     std::vector<int> order(c->ng), chains_m(c->ng, M), chains_p(c->ng, P);
     for (int i = 0; i < c->ng; ++i) order[i] = c->ng - 1 - i;
     std::vector<MoveWork> work, init_work;

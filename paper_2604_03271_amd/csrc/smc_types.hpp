@@ -42,6 +42,8 @@ struct GroupDesc {
     int32_t n, K, d, np, nbg, peak_kind, bg_kind, noise_kind;
     float inv2s2;               // 1 / (2 sigma^2) for Gaussian noise
     int32_t pad0;
+    float hn[3];                // s0^2, s1^2, s2^2 of heteroscedastic noise
+    int32_t pad2;
     const float* x;             // [n]
     const float* y;             // [n]
     const DevPrior* prior;      // [d]

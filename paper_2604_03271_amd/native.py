@@ -17,8 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsmc.so")
 
 PEAK = {"gauss": 0, "pvoigt": 1}
-BG = {"none": 0, "const": 1, "linear": 2}
-NOISE = {"gauss": 0, "poisson": 1}
+BG = {"none": 0, "const": 1, "linear": 2, "shirley": 3}
+NOISE = {"gauss": 0, "poisson": 1, "hetero": 2}
 PRIOR = {"uniform": 0, "gamma": 1, "normal": 2, "fixed": 3}
 
 SMC_OK, SMC_EINVAL, SMC_ENOMEM, SMC_EDEVICE, SMC_ENUMERIC, SMC_ESTATE, SMC_EBUDGET, SMC_EAGAIN = 0, -1, -2, -3, -4, -5, -6, -7
@@ -49,6 +49,7 @@ class smc_problem(ctypes.Structure):
         ("k_min", ctypes.c_int32),
         ("k_max", ctypes.c_int32),
         ("uid", ctypes.c_uint32),
+        ("noise_s", ctypes.c_double * 3),
     ]
 
 
@@ -190,6 +191,9 @@ class Problem:
         p.k_min = int(spec.k_min if k_min is None else k_min)
         p.k_max = int(spec.k_max if k_max is None else k_max)
         p.uid = int(getattr(spec, "uid", 0)) & 0xFFFFFFFF
+        ns = getattr(spec, "noise_s", None) or (0.0, 0.0, 0.0)
+        for q in range(3):
+            p.noise_s[q] = float(ns[q])
         self.c = p
 
     @property

@@ -117,3 +117,31 @@ def test_summary_rejects_bad_arguments():
     assert L.smc_kernel_summary(fake, 4, 0, 0, 3, probs, 2, mean, quant, None) == native.SMC_EINVAL
     assert L.smc_posterior_summary(None, 1, probs, 2, 0, mean, quant) == native.SMC_EINVAL
     assert L.smc_posterior_k(None, mean, 4) == native.SMC_EINVAL
+
+
+def _xps(**kw):
+    sp = W.xps_shirley(index=1, n=300, k_min=2, k_max=3)
+    sp.x = sp.x.copy()
+    sp.y = sp.y.copy()
+    for k, v in kw.items():
+        setattr(sp, k, v)
+    return sp
+
+
+@pytest.mark.parametrize("change", [
+    dict(noise_kind="gauss", sigma=1.0),     # Shirley background needs heteroscedastic noise
+    dict(bg_kind="linear"),                  # heteroscedastic noise needs the Shirley background
+    dict(peak_kind="gauss", peak_prior=[("uniform", 0, 1)] * 3),
+    dict(noise_s=(0.0, 0.0, 0.0)),
+    dict(noise_s=(-1.0, 0.0, 0.0)),
+])
+def test_xps_model_combinations_rejected(change):
+    assert _init_status(_xps(**change)) == native.SMC_EINVAL
+
+
+def test_xps_model_needs_increasing_x_and_at_most_1024_points():
+    sp = _xps()
+    sp.x[10] = sp.x[9]
+    assert _init_status(sp) == native.SMC_EINVAL
+    big = W.xps_shirley(index=1, n=1100, k_min=2, k_max=2)
+    assert _init_status(big) == native.SMC_EINVAL
