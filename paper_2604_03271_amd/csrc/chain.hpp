@@ -239,7 +239,7 @@ __global__ void __launch_bounds__(256) k_energy(const GroupDesc* __restrict__ gr
                                                 const MoveWork* __restrict__ work) {
     using CS = ChainState<PK, NZ, L, WPC, PPL>;
     constexpr int LC = CS::LC;
-    const MoveWork w = work[xcd_block(blockIdx.x, gridDim.x)];
+    const MoveWork w = work[xcd_block(blockIdx.x, gridDim.x, LC / 16)];
     const GroupDesc& g = groups[w.group];
     extern __shared__ float lds[];
     const int slot = threadIdx.x / LC, lane = threadIdx.x % LC;
@@ -265,8 +265,8 @@ __global__ void __launch_bounds__(256) k_energy(const GroupDesc* __restrict__ gr
 // Chain m starts from start[.][m]; standard mode writes its state after the
 // last sweep to particle m, waste-free mode writes the state after sweep t to
 // particle m * n + t (Sec. II.B.3).
-// LDS per chain slot: theta[d], increment s_j z_j [d], ln u_j [d]; then the
-// per-component accept counters [d] and the cross-wave reduction buffer.
+// LDS: the prior table [d]; per chain slot theta[d], increment s_j z_j [d], ln u_j [d];
+// then the per-component accept counters [d] and the cross-wave reduction buffer.
 // ---------------------------------------------------------------------------
 // Waves per SIMD the register allocator is asked to leave room for.  The cached
 // point state grows with PPL (x, D and the shapes: one for a Gaussian peak, two
@@ -288,7 +288,7 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL)) k_move(const
     using CS = ChainState<PK, NZ, L, WPC, PPL>;
     constexpr int LC = CS::LC;
     constexpr int CPW = 256 / LC;
-    const MoveWork w = work[xcd_block(blockIdx.x, gridDim.x)];
+    const MoveWork w = work[xcd_block(blockIdx.x, gridDim.x, LC / 16)];
     const GroupDesc& g = groups[w.group];
     GroupState* st = g.st;
     if (st->done) return;
@@ -297,11 +297,13 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL)) k_move(const
 
     extern __shared__ float lds[];
     const int slot = threadIdx.x / LC, lane = threadIdx.x % LC;
-    float* th = lds + slot * 3 * d;
+    DevPrior* pri = reinterpret_cast<DevPrior*>(lds);   // [d], read once per proposal
+    float* body = lds + 4 * d;
+    float* th = body + slot * 3 * d;
     float* inc = th + d;
     float* lnu = inc + d;
-    uint32_t* accc = reinterpret_cast<uint32_t*>(lds + CPW * 3 * d);
-    float* red = lds + CPW * 3 * d + d;
+    uint32_t* accc = reinterpret_cast<uint32_t*>(body + CPW * 3 * d);
+    float* red = body + CPW * 3 * d + d;
     uint32_t* nevals = reinterpret_cast<uint32_t*>(red + 2 * WPC);   // [0] shape, [1] linear
 
     const bool active = slot < w.nchains;
@@ -311,7 +313,10 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL)) k_move(const
     const uint32_t stage = static_cast<uint32_t>(st->stage);
     const uint32_t K = static_cast<uint32_t>(g.K);
 
-    for (int j = threadIdx.x; j < d; j += 256) accc[j] = 0u;
+    for (int j = threadIdx.x; j < d; j += 256) {
+        accc[j] = 0u;
+        pri[j] = g.prior[j];
+    }
     if (threadIdx.x < 2) nevals[threadIdx.x] = 0u;
     uint32_t my_shape = 0, my_linear = 0;
     float E = 0.0f;
@@ -348,7 +353,7 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL)) k_move(const
                 if (k > 0) cs.transition(g, th, k - 1, k);
                 for (int q = 0; q < nq; ++q) {
                     const int j = j0 + q;
-                    const DevPrior pr = g.prior[j];
+                    const DevPrior pr = pri[j];
                     if (pr.kind == SMC_PRIOR_FIXED) continue;
                     const float vo = th[j];
                     const float vn = vo + inc[j];

@@ -229,7 +229,7 @@ struct XpsChain {
 template <int L, int PPL>
 __global__ void __launch_bounds__(256) k_energy_xps(const GroupDesc* __restrict__ groups,
                                                     const MoveWork* __restrict__ work) {
-    const MoveWork w = work[xcd_block(blockIdx.x, gridDim.x)];
+    const MoveWork w = work[xcd_block(blockIdx.x, gridDim.x, L / 16)];
     const GroupDesc& g = groups[w.group];
     extern __shared__ float lds[];
     const int slot = threadIdx.x / L, lane = threadIdx.x % L;
@@ -254,7 +254,7 @@ template <int L, int PPL>
 __global__ void __launch_bounds__(256, xps_min_waves(PPL)) k_move_xps(const GroupDesc* __restrict__ groups,
                                                                        const MoveWork* __restrict__ work) {
     constexpr int CPW = 256 / L;
-    const MoveWork w = work[xcd_block(blockIdx.x, gridDim.x)];
+    const MoveWork w = work[xcd_block(blockIdx.x, gridDim.x, L / 16)];
     const GroupDesc& g = groups[w.group];
     GroupState* st = g.st;
     if (st->done) return;
@@ -262,11 +262,13 @@ __global__ void __launch_bounds__(256, xps_min_waves(PPL)) k_move_xps(const Grou
 
     extern __shared__ float lds[];
     const int slot = threadIdx.x / L, lane = threadIdx.x % L;
-    float* th = lds + slot * 3 * d;
+    DevPrior* pri = reinterpret_cast<DevPrior*>(lds);   // [d]
+    float* body = lds + 4 * d;
+    float* th = body + slot * 3 * d;
     float* inc = th + d;
     float* lnu = inc + d;
-    uint32_t* accc = reinterpret_cast<uint32_t*>(lds + CPW * 3 * d);
-    uint32_t* nevals = reinterpret_cast<uint32_t*>(lds + CPW * 3 * d + d + 2);   // [0] shape, [1] linear
+    uint32_t* accc = reinterpret_cast<uint32_t*>(body + CPW * 3 * d);
+    uint32_t* nevals = reinterpret_cast<uint32_t*>(body + CPW * 3 * d + d + 2);   // [0] shape, [1] linear
 
     const bool active = slot < w.nchains;
     const int m = w.chain0 + slot;
@@ -276,7 +278,10 @@ __global__ void __launch_bounds__(256, xps_min_waves(PPL)) k_move_xps(const Grou
     const uint32_t K = static_cast<uint32_t>(g.K);
     const int np = g.np, jbg = g.K * g.np;
 
-    for (int j = threadIdx.x; j < d; j += 256) accc[j] = 0u;
+    for (int j = threadIdx.x; j < d; j += 256) {
+        accc[j] = 0u;
+        pri[j] = g.prior[j];
+    }
     if (threadIdx.x < 2) nevals[threadIdx.x] = 0u;
     uint32_t my_shape = 0, my_linear = 0;
     float E = 0.0f;
@@ -308,7 +313,7 @@ __global__ void __launch_bounds__(256, xps_min_waves(PPL)) k_move_xps(const Grou
                 const int nq = is_bg ? g.nbg : np;
                 for (int q = 0; q < nq; ++q) {
                     const int j = j0 + q;
-                    const DevPrior pr = g.prior[j];
+                    const DevPrior pr = pri[j];
                     if (pr.kind == SMC_PRIOR_FIXED) continue;
                     const float vo = th[j];
                     const float vn = vo + inc[j];

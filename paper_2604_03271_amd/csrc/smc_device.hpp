@@ -190,33 +190,50 @@ __device__ __forceinline__ float dpp_swap(float v) {
 // Across rows the gfx950 permlane swaps (VALU, no LDS round trip) return the even
 // and the odd row of each pair of rows (16 lanes), or the low and the high half of
 // the wavefront (32 lanes), in every lane; all lanes add them in the same order.
+// The two results pass through an empty asm before they are added: this compiler
+// otherwise folds the sum of the swap's two results into twice the first one (seen in
+// the assembly as v_add_f32 vN, vN, vN after the swap), which is wrong.
+__device__ __forceinline__ float swap_sum(unsigned a, unsigned b) {
+    asm volatile("" : "+v"(a), "+v"(b));
+    return __builtin_bit_cast(float, a) + __builtin_bit_cast(float, b);
+}
+
+__device__ __forceinline__ float row_pair_sum16(float v) {
+    const unsigned w = __builtin_bit_cast(unsigned, v);
+    const auto p = __builtin_amdgcn_permlane16_swap(w, w, false, false);
+    return swap_sum(p[0], p[1]);
+}
+
+__device__ __forceinline__ float half_pair_sum32(float v) {
+    const unsigned w = __builtin_bit_cast(unsigned, v);
+    const auto p = __builtin_amdgcn_permlane32_swap(w, w, false, false);
+    return swap_sum(p[0], p[1]);
+}
+
 template <int L>
 __device__ __forceinline__ float group_sum(float v) {
     v += dpp_swap<0xB1>(v);   // quad_perm [1,0,3,2]
     v += dpp_swap<0x4E>(v);   // quad_perm [2,3,0,1]
     v += dpp_swap<0x141>(v);  // row_half_mirror: quads of a half-row
     v += dpp_swap<0x140>(v);  // row_mirror: halves of a 16-lane row
-    if constexpr (L >= 32) {
-        const auto p = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, v), __builtin_bit_cast(unsigned, v),
-                                                        false, false);
-        v = __builtin_bit_cast(float, p[0]) + __builtin_bit_cast(float, p[1]);
-    }
-    if constexpr (L >= 64) {
-        const auto p = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, v), __builtin_bit_cast(unsigned, v),
-                                                        false, false);
-        v = __builtin_bit_cast(float, p[0]) + __builtin_bit_cast(float, p[1]);
-    }
+    if constexpr (L >= 32) v = row_pair_sum16(v);
+    if constexpr (L >= 64) v = half_pair_sum32(v);
     return v;
 }
 
-// Logical block of block b in a launch of n blocks: consecutive workgroups go to the
-// 8 XCDs in turn, each with its own L2, so the logical order is re-dealt to give every
-// XCD one contiguous range of work items (neighbouring chains share cache lines of the
-// component-major particle arrays).  A bijection of [0, n).
-__device__ __forceinline__ int xcd_block(int b, int n) {
+// Logical work item of block b in a launch of n blocks.  Consecutive workgroups go to
+// the 8 XCDs in turn, each with its own L2, and neighbouring chains share cache lines of
+// the component-major particle arrays, so items are dealt to the XCDs in chunks of
+// `chunk` consecutive items (chunk c to XCD c mod 8): each XCD reads whole lines, and
+// every group's chains still spread over all XCDs (the work list is ordered by group, so
+// one contiguous range per XCD would give one XCD all of the heaviest group).  The
+// ragged tail of fewer than 8 chunks keeps its order.  A bijection of [0, n).
+__device__ __forceinline__ int xcd_block(int b, int n, int chunk) {
     constexpr int kXcds = 8;
-    const int q = n / kXcds, rem = n % kXcds, x = b % kXcds, r = b / kXcds;
-    return x < rem ? x * (q + 1) + r : rem * (q + 1) + (x - rem) * q + r;
+    const int span = kXcds * chunk;
+    if (b >= (n / span) * span) return b;
+    const int x = b % kXcds, r = b / kXcds;
+    return (x + kXcds * (r / chunk)) * chunk + r % chunk;
 }
 
 }  // namespace smc

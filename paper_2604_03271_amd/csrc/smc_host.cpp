@@ -200,7 +200,7 @@ bool tile_has_kernels(const smc_problem& p, const Tile& t) {
 
 size_t move_lds_bytes(const Tile& t, int d) {
     const int cpw = 256 / t.lanes;
-    return sizeof(float) * (static_cast<size_t>(cpw) * 3 * d + d + 12);
+    return sizeof(DevPrior) * d + sizeof(float) * (static_cast<size_t>(cpw) * 3 * d + d + 12);
 }
 
 size_t energy_lds_bytes(const Tile& t, int d) {

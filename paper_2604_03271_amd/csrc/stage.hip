@@ -401,7 +401,7 @@ __global__ void k_draw(const GroupDesc* __restrict__ groups, int group) {
 // Stage-0 draws of many groups: each work item is a run of <= 256 consecutive draws
 // (linear index j * P + i) of one group.
 __global__ void k_draw_items(const GroupDesc* __restrict__ groups, const MoveWork* __restrict__ items) {
-    const MoveWork w = items[xcd_block(blockIdx.x, gridDim.x)];
+    const MoveWork w = items[blockIdx.x];
     if (static_cast<int>(threadIdx.x) >= w.nchains) return;
     const GroupDesc& g = groups[w.group];
     const int64_t t = static_cast<int64_t>(w.chain0) + threadIdx.x;
