@@ -256,7 +256,13 @@ struct PoolView {
     // One tempering stage of every group.
     hipError_t launch_stage_all(hipStream_t s) const {
         if (groups.empty()) return hipSuccess;
-        hipError_t e = launch_stage(d_groups, static_cast<int>(groups.size()), s);
+        int max_p = 1, max_m = 1, max_d = 1;
+        for (const GroupDesc& g : groups) {
+            max_p = std::max(max_p, g.P);
+            max_m = std::max(max_m, g.M);
+            max_d = std::max(max_d, g.d);
+        }
+        hipError_t e = launch_stage(StageLaunch{d_groups, static_cast<int>(groups.size()), max_p, max_m, max_d}, s);
         if (e != hipSuccess) return e;
         for (const Bucket& b : buckets) {
             const void* mfn = kernels().move[b.pk][b.nz][b.tile.lc][b.tile.pi];

@@ -162,6 +162,39 @@ extern "C" smc_status smc_kernel_energy(const smc_problem* prob, int32_t K, cons
     return finish(s);
 }
 
+// One stand-alone group for the stage hooks: state, trace row, CDF and stage scratch.
+namespace {
+struct StageHook {
+    Scratch scratch;
+    GroupDesc* d_group = nullptr;
+    GroupDesc g{};
+};
+
+smc_status make_stage_hook(StageHook& h, int P, int M, double beta, double rho, int iters, hipStream_t s) {
+    const size_t bytes = 2 * 4096 + sizeof(GroupDesc) + sizeof(GroupState) + sizeof(double) * kTraceCols +
+                         sizeof(unsigned long long) * P + stage_scratch_bytes(P) + 4096;
+    if (hipMalloc(&h.scratch.mem, bytes) != hipSuccess) return SMC_ENOMEM;
+    Arena a{h.scratch.mem, bytes, 0};
+    h.d_group = static_cast<GroupDesc*>(a.take(sizeof(GroupDesc)));
+    GroupState* st = static_cast<GroupState*>(a.take(sizeof(GroupState)));
+    GroupDesc& g = h.g;
+    g.trace = static_cast<double*>(a.take(sizeof(double) * kTraceCols));
+    g.cdf = static_cast<unsigned long long*>(a.take(sizeof(unsigned long long) * P));
+    if (!h.d_group || !st || !g.trace || !g.cdf || !carve_stage_scratch(a, P, g)) return SMC_ENOMEM;
+    g.P = P;
+    g.M = M;
+    g.n_moves = 1;
+    g.st = st;
+    g.rho = rho;
+    g.bisect_iters = iters;
+    g.max_stages = 1;
+    GroupState gs{};
+    gs.beta = beta;
+    if (hipMemcpyAsync(st, &gs, sizeof(gs), hipMemcpyHostToDevice, s) != hipSuccess) return SMC_EDEVICE;
+    return SMC_OK;
+}
+}  // namespace
+
 extern "C" smc_status smc_kernel_ess_bisect(const float* energy, int32_t P, double beta, double rho, int32_t iters,
                                             double* out, void* stream) {
     if (!energy || !out || P < 1 || !(beta >= 0.0 && beta < 1.0) || !(rho > 0.0 && rho < 1.0) || iters < 1 ||
@@ -169,16 +202,28 @@ extern "C" smc_status smc_kernel_ess_bisect(const float* energy, int32_t P, doub
         return SMC_EINVAL;
     if (!device_ok()) return SMC_EDEVICE;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    double* d_out = nullptr;
-    if (hipMalloc(&d_out, sizeof(double) * 4) != hipSuccess) return SMC_ENOMEM;
-    smc_status st = SMC_OK;
-    if (launch_bisect_hook(energy, P, beta, rho, iters, d_out, s) != hipSuccess ||
-        hipMemcpyAsync(out, d_out, sizeof(double) * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+    StageHook h;
+    smc_status st = make_stage_hook(h, P, 1, beta, rho, iters, s);
+    if (st != SMC_OK) return st;
+    h.g.energy = const_cast<float*>(energy);
+    if (hipMemcpyAsync(h.d_group, &h.g, sizeof(GroupDesc), hipMemcpyHostToDevice, s) != hipSuccess ||
+        launch_search_hook(h.d_group, P, s) != hipSuccess)
+        return SMC_EDEVICE;
+    GroupState gs{};
+    StageNewton fin{};
+    if (hipMemcpyAsync(&gs, h.g.st, sizeof(gs), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&fin, h.g.nst + stage_final_parity(), sizeof(fin), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
-        st = SMC_EDEVICE;
-    hipFree(d_out);
-    if (st == SMC_OK && out[0] != out[0]) st = SMC_ENUMERIC;
-    return st;
+        return SMC_EDEVICE;
+    if (gs.status != SMC_OK || fin.phase != kPhaseDone) {
+        out[0] = __builtin_nan("");
+        return SMC_ENUMERIC;
+    }
+    out[0] = gs.delta;
+    out[1] = gs.ess;
+    out[2] = gs.lse;
+    out[3] = fin.emin;
+    return SMC_OK;
 }
 
 extern "C" smc_status smc_kernel_resample(const double* weights, int32_t P, int32_t M, uint32_t r, int32_t* ancestors,
@@ -186,13 +231,14 @@ extern "C" smc_status smc_kernel_resample(const double* weights, int32_t P, int3
     if (!weights || !ancestors || P < 1 || M < 1) return SMC_EINVAL;
     if (!device_ok()) return SMC_EDEVICE;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    unsigned long long* cdf = nullptr;
-    if (hipMalloc(&cdf, sizeof(unsigned long long) * P) != hipSuccess) return SMC_ENOMEM;
-    smc_status st = SMC_OK;
-    if (launch_resample_hook(weights, P, M, r, cdf, ancestors, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
-        st = SMC_EDEVICE;
-    hipFree(cdf);
-    return st;
+    StageHook h;
+    smc_status st = make_stage_hook(h, P, M, 0.0, 0.5, 50, s);
+    if (st != SMC_OK) return st;
+    if (hipMemcpyAsync(h.g.cdf, weights, sizeof(double) * P, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(h.d_group, &h.g, sizeof(GroupDesc), hipMemcpyHostToDevice, s) != hipSuccess ||
+        launch_resample_hook(h.d_group, P, M, r, ancestors, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+        return SMC_EDEVICE;
+    return SMC_OK;
 }
 
 extern "C" smc_status smc_kernel_move(const smc_problem* prob, int32_t K, const float* start_soa, const float* start_e,

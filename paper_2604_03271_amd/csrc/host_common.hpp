@@ -73,11 +73,17 @@ hipError_t upload_group_tables(const Spectrum& sp, const std::vector<GroupDesc>&
 bool device_ok();
 
 // launchers defined in stage.hip
-hipError_t launch_stage(const GroupDesc* groups, int n_groups, hipStream_t s);
+struct StageLaunch {
+    const GroupDesc* groups;  // device array of n_groups descriptors
+    int n_groups, max_p, max_m, max_d;
+};
+hipError_t launch_stage(const StageLaunch& L, hipStream_t s);
+hipError_t launch_search_hook(const GroupDesc* group, int P, hipStream_t s);
+hipError_t launch_resample_hook(const GroupDesc* group, int P, int M, uint32_t r, int32_t* anc, hipStream_t s);
+int stage_final_parity();
+size_t stage_scratch_bytes(int P);
+bool carve_stage_scratch(Arena& a, int P, GroupDesc& g);
 hipError_t launch_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out, int64_t n, hipStream_t s);
-hipError_t launch_bisect_hook(const float* E, int P, double beta, double rho, int iters, double* out, hipStream_t s);
-hipError_t launch_resample_hook(const double* W, int P, int M, uint32_t r, unsigned long long* cdf, int32_t* anc,
-                                hipStream_t s);
 hipError_t launch_draw(const GroupDesc* groups, int group, int64_t n_draws, hipStream_t s);
 hipError_t launch_draw_items(const GroupDesc* groups, const MoveWork* items, int n_items, hipStream_t s);
 

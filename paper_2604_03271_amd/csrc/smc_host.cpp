@@ -319,7 +319,25 @@ size_t group_bytes(int d, int P, int M, int max_stages) {
     const size_t dd = std::max(d, 1);
     return al(sizeof(float) * dd * P) + al(sizeof(float) * P) + al(sizeof(float) * dd * M) + al(sizeof(float) * M) +
            al(sizeof(unsigned long long) * P) + al(sizeof(double) * dd) + al(sizeof(float) * dd) +
-           al(sizeof(uint32_t) * dd) + al(sizeof(DevPrior) * dd) + al(sizeof(double) * kTraceCols * max_stages);
+           al(sizeof(uint32_t) * dd) + al(sizeof(DevPrior) * dd) + al(sizeof(double) * kTraceCols * max_stages) +
+           stage_scratch_bytes(P);
+}
+
+// Scratch of the stage kernels: chunk partial sums [2][nchunk][kStagePartVals], the search
+// state [2] and the chunk totals [nchunk].
+size_t stage_scratch_bytes(int P) {
+    auto al = [](size_t b) { return (b + 255) & ~static_cast<size_t>(255); };
+    const size_t nchunk = (static_cast<size_t>(P) + kStageChunk - 1) / kStageChunk;
+    return al(sizeof(double) * 2 * nchunk * kStagePartVals) + al(sizeof(StageNewton) * 2) +
+           al(sizeof(unsigned long long) * nchunk);
+}
+
+bool carve_stage_scratch(Arena& a, int P, GroupDesc& g) {
+    g.nchunk = (P + kStageChunk - 1) / kStageChunk;
+    g.part = static_cast<double*>(a.take(sizeof(double) * 2 * g.nchunk * kStagePartVals));
+    g.nst = static_cast<StageNewton*>(a.take(sizeof(StageNewton) * 2));
+    g.ctot = static_cast<unsigned long long*>(a.take(sizeof(unsigned long long) * g.nchunk));
+    return g.part && g.nst && g.ctot;
 }
 
 size_t spectrum_bytes(const smc_problem& p, const smc_options& o) {
@@ -379,7 +397,7 @@ bool describe_spectrum(const Spectrum& sp, const smc_options& o, Arena& arena, G
         DevPrior* pri = static_cast<DevPrior*>(arena.take(sizeof(DevPrior) * dd));
         g.trace = static_cast<double*>(arena.take(sizeof(double) * kTraceCols * o.max_stages));
         if (!g.theta || !g.energy || !g.start || !g.start_e || !g.cdf || !g.lambda || !g.step || !g.acc || !pri ||
-            !g.trace)
+            !g.trace || !carve_stage_scratch(arena, P, g))
             return false;
         g.prior = pri;
         g.st = d_states_base + si;
@@ -617,7 +635,10 @@ static smc_status read_states(smc_ctx* c) {
 static hipError_t timed_stage(smc_ctx* c, const GroupDesc* groups, int n) {
     const bool prof = c->opt.profile && !c->ev_stage;
     if (prof && hipEventRecord(c->ev[2], c->stream) != hipSuccess) return hipErrorUnknown;
-    hipError_t e = launch_stage(groups, n, c->stream);
+    int dmax = 1;
+    for (const GroupDesc& g : c->groups) dmax = std::max(dmax, g.d);
+    const int P = c->opt.n_particles, M = c->opt.waste_free ? P / c->opt.n_moves : P;
+    hipError_t e = launch_stage(StageLaunch{groups, n, P, M, dmax}, c->stream);
     if (prof && e == hipSuccess) {
         e = hipEventRecord(c->ev[3], c->stream);
         c->ev_stage = true;

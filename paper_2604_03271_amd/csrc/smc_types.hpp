@@ -37,6 +37,18 @@ struct GroupState {
 
 constexpr int kTraceCols = 6;  // beta, delta, ess, lse, logz, acceptance
 
+// The stage kernels split each group's P particles into chunks of kStageChunk.
+constexpr int kStageChunk = 4096;
+constexpr int kStagePartVals = 6;  // partial sums per chunk
+
+// State of the temperature search of one stage (double-buffered by launch parity).
+enum { kPhaseH = 0, kPhaseNewton = 1, kPhaseDone = 2, kPhaseFail = 3 };
+struct StageNewton {
+    double x, L, U, delta, emin, target, lt, mean, var, nfin;
+    unsigned long long Q;   // total of the quantised weights
+    int32_t phase, iter;
+};
+
 struct GroupDesc {
     // model
     int32_t n, K, d, np, nbg, peak_kind, bg_kind, noise_kind;
@@ -63,6 +75,11 @@ struct GroupDesc {
     int32_t bisect_iters, max_stages;
     uint32_t key0, key1;
     int32_t kidx, pad1;
+    // stage-kernel scratch
+    double* part;               // [2][nchunk][kStagePartVals] chunk partial sums
+    StageNewton* nst;           // [2] temperature-search state
+    unsigned long long* ctot;   // [nchunk] integer weight totals, then their exclusive prefix
+    int32_t nchunk, pad3;
 };
 
 // One workgroup of the move / energy kernels: chains [chain0, chain0 + nchains) of a group.

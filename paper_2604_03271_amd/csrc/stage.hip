@@ -1,17 +1,19 @@
-// stage.hip -- the per-stage bookkeeping of the tempered SMC sampler, one
-// workgroup of 1024 threads per (spectrum, K) group, entirely on the device:
+// stage.hip -- the per-stage bookkeeping of the tempered SMC sampler, entirely on the
+// device, as a pipeline of chunk-parallel launches (described below, before the kernels):
 //
 //   1. step-size multipliers lambda_j from the previous move's acceptance;
-//   2. the next inverse-temperature increment delta by bisection on the ESS of
-//      the incremental weights w_i = exp(-delta E_i) (Eq. smc_incremental_weight);
+//   2. the next inverse-temperature increment delta from the ESS of the incremental
+//      weights w_i = exp(-delta E_i) (Eq. smc_incremental_weight), defined by bisection;
 //   3. log-sum-exp, ESS and the evidence increment LSE - ln P
 //      (Eq. smc_marginal_likelihood), all in FP64;
 //   4. systematic resampling of M ancestors on weights quantised to 2^-52
 //      (integer CDF, 128-bit positions, so the ancestors are exact);
 //   5. gather of the ancestors into the move's start buffer and the
 //      random-walk scales s_j = lambda_j * sd_j over the resampled states.
-// Plus the small kernels behind the per-kernel hooks, which reuse the same
-// device functions.
+// Plus the small kernels behind the per-kernel hooks, which run the same kernels.
+#include <algorithm>
+
+#include "host_common.hpp"
 #include "smc_device.hpp"
 
 namespace smc {
@@ -184,49 +186,6 @@ __device__ inline BisectOut bisect(const float* E, int P, double beta, double rh
     return o;
 }
 
-// Quantise normalised weights to q_i = floor(W_i 2^52) and write the inclusive
-// prefix sums to cdf.  Returns Q = sum q_i (same value in every thread).
-template <class WeightFn>
-__device__ inline unsigned long long quantise_scan(WeightFn weight, int P, unsigned long long* cdf, StageShared& sh) {
-    const int chunk = (P + kStageThreads - 1) / kStageThreads;
-    const int c0 = min(P, static_cast<int>(threadIdx.x) * chunk), c1 = min(P, c0 + chunk);
-    unsigned long long local = 0;
-    for (int i = c0; i < c1; ++i) {
-        const unsigned long long q = static_cast<unsigned long long>(floor(weight(i) * 4503599627370496.0));
-        cdf[i] = q;
-        local += q;
-    }
-    // exclusive scan of the per-thread sums: inside each wave, then over waves
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    unsigned long long incl = local;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const unsigned long long v = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += v;
-    }
-    __syncthreads();
-    if (lane == 63) sh.scan[w] = incl;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long run = 0;
-        for (int q = 0; q < kStageWaves; ++q) {
-            const unsigned long long v = sh.scan[q];
-            sh.scan[q] = run;
-            run += v;
-        }
-        sh.total = run;
-    }
-    __syncthreads();
-    unsigned long long run = sh.scan[w] + incl - local;
-    for (int i = c0; i < c1; ++i) {
-        run += cdf[i];
-        cdf[i] = run;
-    }
-    const unsigned long long Q = sh.total;
-    __syncthreads();
-    return Q;
-}
-
 // floor((m 2^32 + r) Q / (M 2^32)) with a 128-bit product and base-2^32 long division.
 __device__ inline unsigned long long position(uint32_t m, uint32_t r, unsigned long long Q, uint32_t M) {
     const unsigned long long a = (static_cast<unsigned long long>(m) << 32) | r;
@@ -254,110 +213,530 @@ __device__ inline int ancestor(const unsigned long long* cdf, int P, unsigned lo
     return lo;
 }
 
-__global__ void __launch_bounds__(kStageThreads) k_stage(const GroupDesc* __restrict__ groups) {
-    const GroupDesc& g = groups[blockIdx.x];
-    GroupState* st = g.st;
-    __shared__ StageShared sh;
-    __shared__ int s_done;
-    if (st->done) return;
-    const int d = g.d, P = g.P, M = g.M;
-    const int stage_prev = st->stage;
+// ==================================================================== stage pipeline
+//
+// One stage of all groups runs as a short sequence of launches over (group, chunk)
+// workgroups of kChunkThreads threads, each chunk kStageChunk particles, so a stage of
+// one group uses as many CUs as it has chunks.  The launch boundaries order the steps;
+// every reduction over chunks is done in chunk order, redundantly by each workgroup
+// that needs it, so all of them see the same bits:
+//   stats   per chunk: NaN flag, finite count, sum E, sum E^2, min E; chunk 0 also applies
+//           the step-size multipliers of the last move and ends finished groups;
+//   search  kNewtonLaunches launches: reduce the previous launch's chunk sums, advance the
+//           temperature search (ESS at 1 - beta, then the bracketed Newton iteration of
+//           bisect()), and form the chunk sums at the next trial increment;
+//   finish  one workgroup per group that the search left unconverged: bisect() in full;
+//   weights w_i = exp(-delta (E_i - min E)), kept in the CDF buffer, and their chunk sums;
+//   evidence + quantise: ESS, LSE, log Z, trace (chunk 0), then q_i = floor(w_i 2^52 / sum w)
+//           with an inclusive scan inside the chunk and the chunk's total;
+//   offsets exclusive prefix of the chunk totals (one workgroup per group);
+//   resample the ancestor of each of the M positions (search over chunk offsets, then
+//           inside the chunk) and the gather of its state into the move's start buffer;
+//   steps   the random-walk scale of each component over the resampled states.
 
-    // 1. lambda_j <- clamp(lambda_j exp(acc_j - 0.44), 0.01, 10) after a move
-    if (stage_prev > 0 && threadIdx.x == 0) {
-        const double props = static_cast<double>(M) * g.n_moves;
-        double acc_sum = 0.0;
-        int nfree = 0;
-        for (int j = 0; j < d; ++j) {
-            if (g.prior[j].kind == SMC_PRIOR_FIXED) continue;
-            const double a = g.acc[j] / props;
-            acc_sum += a;
-            ++nfree;
-            g.lambda[j] = fmin(10.0, fmax(0.01, g.lambda[j] * exp(a - 0.44)));
-        }
-        if (stage_prev <= g.max_stages) g.trace[(stage_prev - 1) * kTraceCols + 5] = nfree ? acc_sum / nfree : 0.0;
+constexpr int kChunkThreads = 256;
+constexpr int kChunkWaves = kChunkThreads / 64;
+constexpr int kPerThread = kStageChunk / kChunkThreads;
+constexpr int kNewtonLaunches = 10;
+
+__device__ inline StageNewton* nst_buf(const GroupDesc& g, int parity) { return g.nst + (parity & 1); }
+__device__ inline double* part_buf(const GroupDesc& g, int parity) {
+    return g.part + static_cast<size_t>(parity & 1) * g.nchunk * kStagePartVals;
+}
+
+// Sum of NV doubles over the chunk workgroup (fixed order); the result in every thread.
+template <int NV>
+__device__ inline void chunk_block_sum(double* v, double (*red)[kChunkWaves]) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) v[q] += __shfl_xor(v[q], o, 64);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) red[q][w] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < kChunkWaves; ++k) s += red[q][k];
+        v[q] = s;
     }
-    __syncthreads();
-    for (int j = threadIdx.x; j < d; j += kStageThreads) g.acc[j] = 0u;
+}
 
-    if (threadIdx.x == 0) s_done = st->beta >= 1.0 || stage_prev >= g.max_stages;
-    __syncthreads();
-    if (s_done) {
-        if (threadIdx.x == 0) {
+// Reduce the chunk partials parts[c][0..NV) over c = 0..nchunk-1: thread t adds chunks
+// t, t + 256, ... in order, then the fixed block tree.  Value NV-1 is a minimum when
+// MIN_LAST is set.
+template <int NV, bool MIN_LAST>
+__device__ inline void reduce_parts(const double* parts, int nchunk, double* out, double (*red)[kChunkWaves]) {
+    double v[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = (MIN_LAST && q == NV - 1) ? __builtin_inf() : 0.0;
+    for (int c = threadIdx.x; c < nchunk; c += kChunkThreads) {
+        const double* p = parts + static_cast<size_t>(c) * kStagePartVals;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            if (MIN_LAST && q == NV - 1) v[q] = fmin(v[q], p[q]);
+            else v[q] += p[q];
+        }
+    }
+    if constexpr (MIN_LAST) {
+        double m = v[NV - 1];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, 64));
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) red[0][threadIdx.x >> 6] = m;
+        __syncthreads();
+        m = red[0][0];
+#pragma unroll
+        for (int k = 1; k < kChunkWaves; ++k) m = fmin(m, red[0][k]);
+        v[NV - 1] = 0.0;
+        chunk_block_sum<NV>(v, red);
+        v[NV - 1] = m;
+    } else {
+        chunk_block_sum<NV>(v, red);
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q) out[q] = v[q];
+}
+
+// Weight sums of this workgroup's chunk at increment x (NV = 2: sum w, sum w^2; NV = 4
+// also sum a w, sum a w^2 with a = E - emin); optionally keeps w_i in `keep`.
+template <int NV>
+__device__ inline void chunk_weight_sums(const float* E, int i0, int i1, double emin, double x, double* out,
+                                         double* keep, double (*red)[kChunkWaves]) {
+    double v[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = 0.0;
+#pragma unroll 4
+    for (int k = 0; k < kPerThread; ++k) {
+        const int i = i0 + k * kChunkThreads + static_cast<int>(threadIdx.x);
+        if (i < i1) {
+            const double a = static_cast<double>(E[i]) - emin;
+            const double w = exp(-x * a);
+            v[0] += w;
+            v[1] += w * w;
+            if constexpr (NV == 4) {
+                const double aw = w > 0.0 ? a * w : 0.0;
+                v[2] += aw;
+                v[3] += aw * w;
+            }
+            if (keep) keep[i] = w;
+        }
+    }
+    chunk_block_sum<NV>(v, red);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) out[q] = v[q];
+}
+
+// One step of the temperature search from the sums at the last trial point (same rules
+// as bisect()).  it == 0: `sums` are the stats {NaN flag, finite count, sum E, sum E^2, min E}.
+__device__ inline StageNewton search_step(const GroupDesc& g, StageNewton s, const double* sums, int it,
+                                          double beta) {
+    const int P = g.P;
+    if (it == 0) {
+        s = StageNewton{};
+        s.nfin = sums[1];
+        s.emin = sums[4];
+        if (sums[0] != 0.0 || !(s.emin < __builtin_inf())) {
+            s.phase = kPhaseFail;
+            return s;
+        }
+        s.mean = sums[2] / s.nfin;
+        s.var = fmax(sums[3] / s.nfin - s.mean * s.mean, 0.0);
+        s.target = g.rho * static_cast<double>(P);
+        s.lt = log(s.target);
+        s.U = 1.0 - beta;
+        s.x = s.U;
+        s.phase = kPhaseH;
+        return s;
+    }
+    const double H = 1.0 - beta;
+    if (s.phase == kPhaseH) {
+        if (sums[0] * sums[0] / sums[1] >= s.target) {
+            s.delta = H;
+            s.phase = kPhaseDone;
+        } else if (s.nfin < s.target) {
+            double hi = H;
+            for (int k = 0; k < g.bisect_iters; ++k) hi = 0.5 * (0.0 + hi);
+            s.delta = hi;
+            s.phase = kPhaseDone;
+        } else {
+            s.L = 0.0;
+            s.U = H;
+            double x = s.var > 0.0 ? sqrt((1.0 / g.rho - 1.0) / s.var) : 0.5 * H;
+            if (!(x > s.L && x < s.U)) x = 0.5 * H;
+            s.x = x;
+            s.iter = 0;
+            s.phase = kPhaseNewton;
+        }
+        return s;
+    }
+    if (s.phase != kPhaseNewton) return s;
+    const double x = s.x;
+    const double gv = 2.0 * log(sums[0]) - log(sums[1]) - s.lt;
+    const double gp = 2.0 * (sums[3] / sums[1] - sums[2] / sums[0]);
+    if (gv >= 0.0) s.L = x;
+    else s.U = x;
+    const bool newton = gp < 0.0;
+    const double step = newton ? -gv / gp : 0.0;
+    double r = -1.0;
+    if (newton && fabs(step) <= 4e-16 * x) r = fmin(fmax(x + step, s.L), s.U);
+    else if (s.U - s.L <= 1e-15 * s.U) r = 0.5 * (s.L + s.U);
+    if (r >= 0.0) {
+        double lo = 0.0, hi = H;
+        for (int k = 0; k < g.bisect_iters; ++k) {
+            const double mid = 0.5 * (lo + hi);
+            if (mid <= r) lo = mid;
+            else hi = mid;
+        }
+        s.delta = lo > 0.0 ? lo : hi;
+        s.phase = kPhaseDone;
+        return s;
+    }
+    double xn = x + step;
+    if (!newton || !(xn > s.L && xn < s.U)) xn = s.L > 0.0 ? sqrt(s.L * s.U) : 0.125 * s.U;
+    s.x = xn;
+    ++s.iter;
+    return s;
+}
+
+// chunk index range of workgroup (group, c)
+__device__ inline void chunk_range(const GroupDesc& g, int c, int& i0, int& i1) {
+    i0 = c * kStageChunk;
+    i1 = min(g.P, i0 + kStageChunk);
+}
+
+__global__ void __launch_bounds__(kChunkThreads) k_st_stats(const GroupDesc* __restrict__ groups, int maxch) {
+    const int gi = blockIdx.x / maxch, c = blockIdx.x % maxch;
+    const GroupDesc& g = groups[gi];
+    GroupState* st = g.st;
+    if (c >= g.nchunk || st->done) return;
+    __shared__ double red[kStagePartVals][kChunkWaves];
+    if (c == 0) {
+        // lambda_j <- clamp(lambda_j exp(acc_j - 0.44), 0.01, 10) after a move; end finished groups
+        const int stage_prev = st->stage;
+        if (stage_prev > 0 && threadIdx.x == 0) {
+            const double props = static_cast<double>(g.M) * g.n_moves;
+            double acc_sum = 0.0;
+            int nfree = 0;
+            for (int j = 0; j < g.d; ++j) {
+                if (g.prior[j].kind == SMC_PRIOR_FIXED) continue;
+                const double a = g.acc[j] / props;
+                acc_sum += a;
+                ++nfree;
+                g.lambda[j] = fmin(10.0, fmax(0.01, g.lambda[j] * exp(a - 0.44)));
+            }
+            if (stage_prev <= g.max_stages) g.trace[(stage_prev - 1) * kTraceCols + 5] = nfree ? acc_sum / nfree : 0.0;
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < g.d; j += kChunkThreads) g.acc[j] = 0u;
+        if (threadIdx.x == 0 && (st->beta >= 1.0 || stage_prev >= g.max_stages)) {
             if (st->beta < 1.0) st->status = SMC_ENUMERIC;
             st->done = 1;
         }
-        return;
     }
-    const int stage = stage_prev + 1;
-    const double beta = st->beta;
-
-    // 2-3. temperature, weights, evidence
-    const BisectOut b = bisect(g.energy, P, beta, g.rho, g.bisect_iters, sh);
-    if (!b.ok) {
-        if (threadIdx.x == 0) {
-            st->status = SMC_ENUMERIC;
-            st->done = 1;
+    int i0, i1;
+    chunk_range(g, c, i0, i1);
+    double v[5] = {0.0, 0.0, 0.0, 0.0, __builtin_inf()};
+#pragma unroll 4
+    for (int k = 0; k < kPerThread; ++k) {
+        const int i = i0 + k * kChunkThreads + static_cast<int>(threadIdx.x);
+        if (i < i1) {
+            const float e = g.energy[i];
+            if (__builtin_isnan(e)) v[0] = 1.0;
+            if (__builtin_isfinite(e)) {
+                const double x = static_cast<double>(e);
+                v[1] += 1.0;
+                v[2] += x;
+                v[3] += x * x;
+            }
+            v[4] = fmin(v[4], static_cast<double>(e));
         }
-        return;
     }
-    double beta_new = (b.delta == 1.0 - beta) ? 1.0 : beta + b.delta;
-    if (beta_new > 1.0) beta_new = 1.0;
-    const double s1 = b.s1, emin = b.emin, delta = b.delta;
+    double m = v[4];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, 64));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[5][threadIdx.x >> 6] = m;
+    chunk_block_sum<4>(v, red);
+    if (threadIdx.x == 0) {
+        m = red[5][0];
+#pragma unroll
+        for (int k = 1; k < kChunkWaves; ++k) m = fmin(m, red[5][k]);
+        double* out = part_buf(g, 0) + static_cast<size_t>(c) * kStagePartVals;
+        for (int q = 0; q < 4; ++q) out[q] = v[q];
+        out[4] = m;
+    }
+}
 
-    // 4. resampling
-    const float* E = g.energy;
-    const unsigned long long Q = quantise_scan(
-        [=](int i) { return exp(-delta * (static_cast<double>(E[i]) - emin)) / s1; }, P, g.cdf, sh);
-    const uint32_t r = draw(g.key0, g.key1, 0u, static_cast<uint32_t>(stage), 0u, static_cast<uint32_t>(g.K),
-                            kPurposeResample).x;
-    for (int m = threadIdx.x; m < M; m += kStageThreads) {
-        const int a = ancestor(g.cdf, P, position(static_cast<uint32_t>(m), r, Q, static_cast<uint32_t>(M)));
-        g.start_e[m] = E[a];
-        for (int j = 0; j < d; ++j) g.start[(size_t)j * M + m] = g.theta[(size_t)j * P + a];
+__global__ void __launch_bounds__(kChunkThreads) k_st_search(const GroupDesc* __restrict__ groups, int maxch, int it) {
+    const int gi = blockIdx.x / maxch, c = blockIdx.x % maxch;
+    const GroupDesc& g = groups[gi];
+    GroupState* st = g.st;
+    if (c >= g.nchunk || st->done) return;
+    __shared__ double red[kStagePartVals][kChunkWaves];
+    __shared__ StageNewton s_nst;
+    StageNewton prev{};
+    if (it > 0) {
+        prev = *nst_buf(g, it);
+        if (prev.phase == kPhaseDone || prev.phase == kPhaseFail) {
+            if (c == 0 && threadIdx.x == 0) *nst_buf(g, it + 1) = prev;
+            return;
+        }
+    }
+    double sums[5];
+    if (it == 0) reduce_parts<5, true>(part_buf(g, 0), g.nchunk, sums, red);
+    else reduce_parts<4, false>(part_buf(g, it), g.nchunk, sums, red);
+    if (threadIdx.x == 0) {
+        const StageNewton ns = search_step(g, prev, sums, it, st->beta);
+        s_nst = ns;
+        if (c == 0) {
+            *nst_buf(g, it + 1) = ns;
+            if (ns.phase == kPhaseFail) {
+                st->status = SMC_ENUMERIC;
+                st->done = 1;
+            }
+        }
     }
     __syncthreads();
-
-    // 5. step sizes over the resampled states (one wave per component)
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int j = w; j < d; j += kStageWaves) {
-        if (g.prior[j].kind == SMC_PRIOR_FIXED) {
-            if (lane == 0) g.step[j] = 0.0f;
-            continue;
-        }
-        const float* col = g.start + (size_t)j * M;
-        double sum = 0.0;
-        for (int m = lane; m < M; m += 64) sum += col[m];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
-        const double mean = sum / M;
-        double ss = 0.0;
-        for (int m = lane; m < M; m += 64) {
-            const double c = col[m] - mean;
-            ss += c * c;
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
-        const double sd = sqrt(ss / M);
-        const double fl = 1e-12 * (fabs(mean) + 1.0);
-        if (lane == 0) g.step[j] = static_cast<float>(g.lambda[j] * (sd > fl ? sd : fl));
+    const StageNewton ns = s_nst;
+    if (ns.phase != kPhaseH && ns.phase != kPhaseNewton) return;
+    int i0, i1;
+    chunk_range(g, c, i0, i1);
+    double out[4];
+    if (ns.phase == kPhaseH) {
+        chunk_weight_sums<2>(g.energy, i0, i1, ns.emin, ns.x, out, nullptr, red);
+        out[2] = out[3] = 0.0;
+    } else {
+        chunk_weight_sums<4>(g.energy, i0, i1, ns.emin, ns.x, out, nullptr, red);
     }
-
     if (threadIdx.x == 0) {
-        st->logz += b.lse - log(static_cast<double>(P));
+        double* p = part_buf(g, it + 1) + static_cast<size_t>(c) * kStagePartVals;
+        for (int q = 0; q < 4; ++q) p[q] = out[q];
+    }
+}
+
+// Groups whose search did not converge within the launches: the full search in one
+// workgroup (bisect() from the start; not seen in practice).
+__global__ void __launch_bounds__(kStageThreads) k_st_finish(const GroupDesc* __restrict__ groups) {
+    const GroupDesc& g = groups[blockIdx.x];
+    GroupState* st = g.st;
+    if (st->done) return;
+    StageNewton* fin = nst_buf(g, kNewtonLaunches);
+    if (fin->phase == kPhaseDone) return;
+    __shared__ StageShared sh;
+    const BisectOut b = bisect(g.energy, g.P, st->beta, g.rho, g.bisect_iters, sh);
+    if (threadIdx.x == 0) {
+        if (!b.ok) {
+            fin->phase = kPhaseFail;
+            st->status = SMC_ENUMERIC;
+            st->done = 1;
+        } else {
+            fin->delta = b.delta;
+            fin->emin = b.emin;
+            fin->phase = kPhaseDone;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kChunkThreads) k_st_weights(const GroupDesc* __restrict__ groups, int maxch) {
+    const int gi = blockIdx.x / maxch, c = blockIdx.x % maxch;
+    const GroupDesc& g = groups[gi];
+    if (c >= g.nchunk || g.st->done) return;
+    __shared__ double red[kStagePartVals][kChunkWaves];
+    const StageNewton fin = *nst_buf(g, kNewtonLaunches);
+    int i0, i1;
+    chunk_range(g, c, i0, i1);
+    double out[2];
+    chunk_weight_sums<2>(g.energy, i0, i1, fin.emin, fin.delta, out, reinterpret_cast<double*>(g.cdf), red);
+    if (threadIdx.x == 0) {
+        double* p = part_buf(g, 0) + static_cast<size_t>(c) * kStagePartVals;
+        p[0] = out[0];
+        p[1] = out[1];
+    }
+}
+
+// Evidence update (chunk 0) and the quantised weights with their scan inside the chunk.
+// With unit_sum set the weights in the CDF buffer are taken as already normalised.
+__global__ void __launch_bounds__(kChunkThreads) k_st_quantise(const GroupDesc* __restrict__ groups, int maxch,
+                                                               int unit_sum) {
+    const int gi = blockIdx.x / maxch, c = blockIdx.x % maxch;
+    const GroupDesc& g = groups[gi];
+    GroupState* st = g.st;
+    if (c >= g.nchunk || st->done) return;
+    __shared__ double red[kStagePartVals][kChunkWaves];
+    __shared__ unsigned long long s_scan[kChunkWaves];
+    double sums[2];
+    if (unit_sum) {
+        sums[0] = 1.0;
+        sums[1] = 1.0;
+    } else {
+        reduce_parts<2, false>(part_buf(g, 0), g.nchunk, sums, red);
+    }
+    const double s1 = sums[0];
+    if (c == 0 && threadIdx.x == 0 && !unit_sum) {
+        const StageNewton fin = *nst_buf(g, kNewtonLaunches);
+        const double delta = fin.delta, beta = st->beta;
+        double beta_new = (delta == 1.0 - beta) ? 1.0 : beta + delta;
+        if (beta_new > 1.0) beta_new = 1.0;
+        const double ess = s1 * s1 / sums[1];
+        const double lse = -delta * fin.emin + log(s1);
+        const int stage = st->stage + 1;
+        st->logz += lse - log(static_cast<double>(g.P));
         st->beta = beta_new;
         st->delta = delta;
-        st->ess = b.ess;
-        st->lse = b.lse;
+        st->ess = ess;
+        st->lse = lse;
         st->stage = stage;
-        double* tr = g.trace + (stage - 1) * kTraceCols;
-        tr[0] = beta_new;
-        tr[1] = delta;
-        tr[2] = b.ess;
-        tr[3] = b.lse;
-        tr[4] = st->logz;
-        tr[5] = 0.0;
+        if (stage <= g.max_stages) {
+            double* tr = g.trace + (stage - 1) * kTraceCols;
+            tr[0] = beta_new;
+            tr[1] = delta;
+            tr[2] = ess;
+            tr[3] = lse;
+            tr[4] = st->logz;
+            tr[5] = 0.0;
+        }
     }
+    // thread t owns the kPerThread consecutive weights t*kPerThread.. of the chunk
+    int i0, i1;
+    chunk_range(g, c, i0, i1);
+    const double* w = reinterpret_cast<const double*>(g.cdf);
+    unsigned long long q[kPerThread];
+    unsigned long long local = 0;
+    const int base = i0 + static_cast<int>(threadIdx.x) * kPerThread;
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+        const int i = base + k;
+        q[k] = i < i1 ? static_cast<unsigned long long>(floor(w[i] / s1 * 4503599627370496.0)) : 0ull;
+        local += q[k];
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    unsigned long long incl = local;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+    }
+    __syncthreads();   // every weight of the chunk read before any is overwritten
+    if (lane == 63) s_scan[wv] = incl;
+    __syncthreads();
+    unsigned long long run = incl - local;
+#pragma unroll
+    for (int k = 0; k < kChunkWaves; ++k)
+        if (k < wv) run += s_scan[k];
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+        const int i = base + k;
+        run += q[k];
+        if (i < i1) g.cdf[i] = run;
+    }
+    if (threadIdx.x == kChunkThreads - 1) {
+        unsigned long long tot = 0;
+#pragma unroll
+        for (int k = 0; k < kChunkWaves; ++k) tot += s_scan[k];
+        g.ctot[c] = tot;
+    }
+}
+
+// Exclusive prefix of the chunk totals, in place, and their grand total Q (kept in the
+// final search state).
+__global__ void __launch_bounds__(kChunkThreads) k_st_offsets(const GroupDesc* __restrict__ groups) {
+    const GroupDesc& g = groups[blockIdx.x];
+    if (g.st->done) return;
+    __shared__ unsigned long long s_scan[kChunkWaves];
+    __shared__ unsigned long long s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int c0 = 0; c0 < g.nchunk; c0 += kChunkThreads) {
+        const int c = c0 + static_cast<int>(threadIdx.x);
+        const unsigned long long v = c < g.nchunk ? g.ctot[c] : 0ull;
+        unsigned long long incl = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned long long u = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += u;
+        }
+        if (lane == 63) s_scan[wv] = incl;
+        __syncthreads();
+        unsigned long long off = s_carry + incl - v;
+#pragma unroll
+        for (int k = 0; k < kChunkWaves; ++k)
+            if (k < wv) off += s_scan[k];
+        if (c < g.nchunk) g.ctot[c] = off;
+        __syncthreads();
+        if (threadIdx.x == kChunkThreads - 1) s_carry = off + v;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) nst_buf(g, kNewtonLaunches)->Q = s_carry;
+}
+
+// Ancestor of position m and the gather of its state.  r_fixed >= 0 replaces the drawn
+// uniform (hook).  anc (optional) receives the ancestors.
+__global__ void __launch_bounds__(kChunkThreads) k_st_resample(const GroupDesc* __restrict__ groups, int mblocks,
+                                                               int64_t r_fixed, int32_t* __restrict__ anc) {
+    const int gi = blockIdx.x / mblocks, mb = blockIdx.x % mblocks;
+    const GroupDesc& g = groups[gi];
+    GroupState* st = g.st;
+    const int m = mb * kChunkThreads + static_cast<int>(threadIdx.x);
+    if (st->done || m >= g.M) return;
+    const StageNewton fin = *nst_buf(g, kNewtonLaunches);
+    const unsigned long long Q = fin.Q;
+    const uint32_t r = r_fixed >= 0 ? static_cast<uint32_t>(r_fixed)
+                                    : draw(g.key0, g.key1, 0u, static_cast<uint32_t>(st->stage), 0u,
+                                           static_cast<uint32_t>(g.K), kPurposeResample).x;
+    const unsigned long long pos = position(static_cast<uint32_t>(m), r, Q, static_cast<uint32_t>(g.M));
+    // chunk: the first c whose end (offset of c + 1, or Q) exceeds pos
+    int lo = 0, hi = g.nchunk - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const unsigned long long end = mid + 1 < g.nchunk ? g.ctot[mid + 1] : Q;
+        if (end > pos) hi = mid;
+        else lo = mid + 1;
+    }
+    const unsigned long long rel = pos - g.ctot[lo];
+    int i0, i1;
+    chunk_range(g, lo, i0, i1);
+    int a = i0 + ancestor(g.cdf + i0, i1 - i0, rel);
+    if (anc) anc[m] = a;
+    if (g.theta) {
+        g.start_e[m] = g.energy[a];
+        for (int j = 0; j < g.d; ++j) g.start[(size_t)j * g.M + m] = g.theta[(size_t)j * g.P + a];
+    }
+}
+
+// Random-walk scales s_j = lambda_j * sd_j over the resampled states (one wave per component).
+__global__ void __launch_bounds__(kChunkThreads) k_st_steps(const GroupDesc* __restrict__ groups, int jblocks) {
+    const int gi = blockIdx.x / jblocks, jb = blockIdx.x % jblocks;
+    const GroupDesc& g = groups[gi];
+    const int lane = threadIdx.x & 63;
+    const int j = jb * kChunkWaves + static_cast<int>(threadIdx.x >> 6);
+    if (g.st->done || j >= g.d) return;
+    if (g.prior[j].kind == SMC_PRIOR_FIXED) {
+        if (lane == 0) g.step[j] = 0.0f;
+        return;
+    }
+    const int M = g.M;
+    const float* col = g.start + (size_t)j * M;
+    double sum = 0.0;
+    for (int m = lane; m < M; m += 64) sum += col[m];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+    const double mean = sum / M;
+    double ss = 0.0;
+    for (int m = lane; m < M; m += 64) {
+        const double dd = col[m] - mean;
+        ss += dd * dd;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
+    const double sd = sqrt(ss / M);
+    const double fl = 1e-12 * (fabs(mean) + 1.0);
+    if (lane == 0) g.step[j] = static_cast<float>(g.lambda[j] * (sd > fl ? sd : fl));
 }
 
 // ------------------------------------------------------------------ hook kernels
@@ -365,27 +744,6 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(const GroupDesc* __rest
 __global__ void k_philox(const uint4* __restrict__ ctr, uint32_t k0, uint32_t k1, uint4* __restrict__ out, int64_t n) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) out[i] = philox(ctr[i], k0, k1);
-}
-
-__global__ void __launch_bounds__(kStageThreads) k_bisect_hook(const float* __restrict__ E, int P, double beta, double rho,
-                                                              int iters, double* __restrict__ out) {
-    __shared__ StageShared sh;
-    const BisectOut b = bisect(E, P, beta, rho, iters, sh);
-    if (threadIdx.x == 0) {
-        out[0] = b.ok ? b.delta : __builtin_nan("");
-        out[1] = b.ess;
-        out[2] = b.lse;
-        out[3] = b.emin;
-    }
-}
-
-__global__ void __launch_bounds__(kStageThreads) k_resample_hook(const double* __restrict__ W, int P, int M, uint32_t r,
-                                                                unsigned long long* __restrict__ cdf,
-                                                                int32_t* __restrict__ anc) {
-    __shared__ StageShared sh;
-    const unsigned long long Q = quantise_scan([=](int i) { return W[i]; }, P, cdf, sh);
-    for (int m = threadIdx.x; m < M; m += kStageThreads)
-        anc[m] = ancestor(cdf, P, position(static_cast<uint32_t>(m), r, Q, static_cast<uint32_t>(M)));
 }
 
 // Stage 0 draws: one thread per (particle, component).
@@ -419,10 +777,47 @@ hipError_t launch_draw_items(const GroupDesc* groups, const MoveWork* items, int
 }
 
 
-hipError_t launch_stage(const GroupDesc* groups, int n_groups, hipStream_t s) {
-    hipLaunchKernelGGL(k_stage, dim3(n_groups), dim3(kStageThreads), 0, s, groups);
+hipError_t launch_stage(const StageLaunch& L, hipStream_t s) {
+    if (L.n_groups <= 0) return hipSuccess;
+    const int maxch = (L.max_p + kStageChunk - 1) / kStageChunk;
+    const dim3 nb(static_cast<unsigned>(L.n_groups * maxch));
+    hipLaunchKernelGGL(k_st_stats, nb, dim3(kChunkThreads), 0, s, L.groups, maxch);
+    for (int it = 0; it < kNewtonLaunches; ++it)
+        hipLaunchKernelGGL(k_st_search, nb, dim3(kChunkThreads), 0, s, L.groups, maxch, it);
+    hipLaunchKernelGGL(k_st_finish, dim3(L.n_groups), dim3(kStageThreads), 0, s, L.groups);
+    hipLaunchKernelGGL(k_st_weights, nb, dim3(kChunkThreads), 0, s, L.groups, maxch);
+    hipLaunchKernelGGL(k_st_quantise, nb, dim3(kChunkThreads), 0, s, L.groups, maxch, 0);
+    hipLaunchKernelGGL(k_st_offsets, dim3(L.n_groups), dim3(kChunkThreads), 0, s, L.groups);
+    const int mblocks = (L.max_m + kChunkThreads - 1) / kChunkThreads;
+    hipLaunchKernelGGL(k_st_resample, dim3(L.n_groups * mblocks), dim3(kChunkThreads), 0, s, L.groups, mblocks,
+                       int64_t{-1}, static_cast<int32_t*>(nullptr));
+    const int jblocks = (std::max(L.max_d, 1) + kChunkWaves - 1) / kChunkWaves;
+    hipLaunchKernelGGL(k_st_steps, dim3(L.n_groups * jblocks), dim3(kChunkThreads), 0, s, L.groups, jblocks);
     return hipGetLastError();
 }
+
+hipError_t launch_search_hook(const GroupDesc* group, int P, hipStream_t s) {
+    const int maxch = (P + kStageChunk - 1) / kStageChunk;
+    hipLaunchKernelGGL(k_st_stats, dim3(maxch), dim3(kChunkThreads), 0, s, group, maxch);
+    for (int it = 0; it < kNewtonLaunches; ++it)
+        hipLaunchKernelGGL(k_st_search, dim3(maxch), dim3(kChunkThreads), 0, s, group, maxch, it);
+    hipLaunchKernelGGL(k_st_finish, dim3(1), dim3(kStageThreads), 0, s, group);
+    hipLaunchKernelGGL(k_st_weights, dim3(maxch), dim3(kChunkThreads), 0, s, group, maxch);
+    hipLaunchKernelGGL(k_st_quantise, dim3(maxch), dim3(kChunkThreads), 0, s, group, maxch, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_resample_hook(const GroupDesc* group, int P, int M, uint32_t r, int32_t* anc, hipStream_t s) {
+    const int maxch = (P + kStageChunk - 1) / kStageChunk;
+    hipLaunchKernelGGL(k_st_quantise, dim3(maxch), dim3(kChunkThreads), 0, s, group, maxch, 1);
+    hipLaunchKernelGGL(k_st_offsets, dim3(1), dim3(kChunkThreads), 0, s, group);
+    const int mblocks = (M + kChunkThreads - 1) / kChunkThreads;
+    hipLaunchKernelGGL(k_st_resample, dim3(mblocks), dim3(kChunkThreads), 0, s, group, mblocks, int64_t{r}, anc);
+    return hipGetLastError();
+}
+
+// Index of the final temperature-search state (read by the hooks).
+int stage_final_parity() { return kNewtonLaunches & 1; }
 
 hipError_t launch_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out, int64_t n, hipStream_t s) {
     const int64_t blocks = (n + 255) / 256;
@@ -431,16 +826,7 @@ hipError_t launch_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t
     return hipGetLastError();
 }
 
-hipError_t launch_bisect_hook(const float* E, int P, double beta, double rho, int iters, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_bisect_hook, dim3(1), dim3(kStageThreads), 0, s, E, P, beta, rho, iters, out);
-    return hipGetLastError();
-}
 
-hipError_t launch_resample_hook(const double* W, int P, int M, uint32_t r, unsigned long long* cdf, int32_t* anc,
-                                hipStream_t s) {
-    hipLaunchKernelGGL(k_resample_hook, dim3(1), dim3(kStageThreads), 0, s, W, P, M, r, cdf, anc);
-    return hipGetLastError();
-}
 
 hipError_t launch_draw(const GroupDesc* groups, int group, int64_t n_draws, hipStream_t s) {
     if (n_draws <= 0) return hipSuccess;
