@@ -213,6 +213,7 @@ def main():
     ap.add_argument("--batch", type=int, default=0, help="also run the config-4 batch with this many spectra")
     ap.add_argument("--serve", type=int, default=0, help="also serve this many config-5 arrivals")
     ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--rates", default="", help="comma-separated arrival rates: serve --serve arrivals at each")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one device-to-device copy of this many bytes (calibrates HBM counters)")
     args = ap.parse_args()
@@ -318,6 +319,8 @@ def main():
         out["batched"] = batched(native, workloads, args.batch)
     if args.serve:
         out["served"] = served(native, workloads, args.serve, args.rate)
+        if args.rates:
+            out["served_sweep"] = [served(native, workloads, args.serve, float(r)) for r in args.rates.split(",")]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, 5 if args.workload == "xps-pv" else spec.truth["K"])
     s.close()

@@ -416,23 +416,26 @@ __global__ void __launch_bounds__(kChunkThreads) k_st_stats(const GroupDesc* __r
     if (c >= g.nchunk || st->done) return;
     __shared__ double red[kStagePartVals][kChunkWaves];
     if (c == 0) {
-        // lambda_j <- clamp(lambda_j exp(acc_j - 0.44), 0.01, 10) after a move; end finished groups
+        // lambda_j <- clamp(lambda_j exp(acc_j - 0.44), 0.01, 10) after a move (thread j), the
+        // stage's mean acceptance into the trace; end finished groups
         const int stage_prev = st->stage;
-        if (stage_prev > 0 && threadIdx.x == 0) {
+        if (stage_prev > 0) {
             const double props = static_cast<double>(g.M) * g.n_moves;
-            double acc_sum = 0.0;
-            int nfree = 0;
-            for (int j = 0; j < g.d; ++j) {
+            double v[2] = {0.0, 0.0};   // sum of acceptance rates, free components
+            for (int j = threadIdx.x; j < g.d; j += kChunkThreads) {
                 if (g.prior[j].kind == SMC_PRIOR_FIXED) continue;
                 const double a = g.acc[j] / props;
-                acc_sum += a;
-                ++nfree;
+                v[0] += a;
+                v[1] += 1.0;
                 g.lambda[j] = fmin(10.0, fmax(0.01, g.lambda[j] * exp(a - 0.44)));
+                g.acc[j] = 0u;
             }
-            if (stage_prev <= g.max_stages) g.trace[(stage_prev - 1) * kTraceCols + 5] = nfree ? acc_sum / nfree : 0.0;
+            chunk_block_sum<2>(v, red);
+            if (threadIdx.x == 0 && stage_prev <= g.max_stages)
+                g.trace[(stage_prev - 1) * kTraceCols + 5] = v[1] > 0.0 ? v[0] / v[1] : 0.0;
+        } else {
+            for (int j = threadIdx.x; j < g.d; j += kChunkThreads) g.acc[j] = 0u;
         }
-        __syncthreads();
-        for (int j = threadIdx.x; j < g.d; j += kChunkThreads) g.acc[j] = 0u;
         if (threadIdx.x == 0 && (st->beta >= 1.0 || stage_prev >= g.max_stages)) {
             if (st->beta < 1.0) st->status = SMC_ENUMERIC;
             st->done = 1;
@@ -722,16 +725,26 @@ __global__ void __launch_bounds__(kChunkThreads) k_st_steps(const GroupDesc* __r
     }
     const int M = g.M;
     const float* col = g.start + (size_t)j * M;
-    double sum = 0.0;
-    for (int m = lane; m < M; m += 64) sum += col[m];
+    // four independent accumulators per lane keep several loads in flight
+    double acc4[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int m0 = lane; m0 < M; m0 += 256)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (m0 + 64 * u < M) acc4[u] += col[m0 + 64 * u];
+    double sum = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
     const double mean = sum / M;
-    double ss = 0.0;
-    for (int m = lane; m < M; m += 64) {
-        const double dd = col[m] - mean;
-        ss += dd * dd;
-    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc4[u] = 0.0;
+    for (int m0 = lane; m0 < M; m0 += 256)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (m0 + 64 * u < M) {
+                const double dd = col[m0 + 64 * u] - mean;
+                acc4[u] += dd * dd;
+            }
+    double ss = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
     const double sd = sqrt(ss / M);
