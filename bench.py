@@ -148,6 +148,11 @@ def batched(native, workloads, n_spectra, P=8192, plain_sample=4):
             "plain_note": f"same kernels, one spectrum and one K at a time, measured on {plain_sample} of them"}
 
 
+def progress(*a):
+    """A progress line on stderr (long phases must not look idle)."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
 def served(native, workloads, n_arrivals, rate, budget=64 << 30):
     """Config 5: Poisson(rate) arrivals, 70% config-1-shaped and 30% config-2-shaped requests,
     submitted in real time to the continuous-batching server."""
@@ -168,6 +173,8 @@ def served(native, workloads, n_arrivals, rate, budget=64 << 30):
         for r in srv.poll(1):
             got[r["id"]] = r
             lat.append(r["latency_s"])
+            if len(got) % 50 == 0:
+                progress(f"served {len(got)}/{n_arrivals} at rate {rate}")
     dur = time.perf_counter() - t0
     srv.close()
     lat = np.array(lat)
@@ -246,6 +253,7 @@ def main():
     kinds = {"stage0": 0, "shape": 0, "linear": 0}
     t0 = time.perf_counter()
     for k in range(args.steps):
+        progress(f"step {k + 1}/{args.steps}")
         ts = time.perf_counter()
         s.reset(k + 1)
         s.run()
