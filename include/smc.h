@@ -67,6 +67,9 @@ enum { SMC_BG_NONE = 0, SMC_BG_CONST = 1, SMC_BG_LINEAR = 2, SMC_BG_SHIRLEY = 3 
 enum { SMC_NOISE_GAUSS = 0, SMC_NOISE_POISSON = 1, SMC_NOISE_HETERO = 2 };
 enum { SMC_PRIOR_UNIFORM = 0, SMC_PRIOR_GAMMA = 1, SMC_PRIOR_NORMAL = 2, SMC_PRIOR_FIXED = 3 };
 
+#define SMC_MAX_PEAK_PARAMS 9   /* parameters of one peak (XRD peaks have the most) */
+#define SMC_MAX_BG_PARAMS 4     /* background parameters (XRD background has the most) */
+
 /* Priors of the paper's tables (spectral_priors, xrd_priors, xps_priors):
  * UNIFORM(a = lo, b = hi) on the open interval, GAMMA(a = shape, b = rate),
  * NORMAL(a = mean, b = standard deviation), FIXED(a = value; not sampled). */
@@ -93,9 +96,9 @@ typedef struct {
     int32_t bg_kind;             /* SMC_BG_* */
     int32_t noise_kind;          /* SMC_NOISE_* */
     double sigma;                /* noise standard deviation (Gaussian noise), > 0 */
-    smc_prior peak_prior[4];     /* prior of each peak parameter, shared by all peaks */
-    smc_prior bg_prior[2];       /* prior of each background parameter */
-    const smc_prior* peak_prior_k; /* (host) optional [k_max][4] per-peak priors; NULL = peak_prior */
+    smc_prior peak_prior[SMC_MAX_PEAK_PARAMS];  /* prior of each peak parameter, shared by all peaks */
+    smc_prior bg_prior[SMC_MAX_BG_PARAMS];      /* prior of each background parameter */
+    const smc_prior* peak_prior_k; /* (host) optional [k_max][SMC_MAX_PEAK_PARAMS] per-peak priors; NULL = peak_prior */
     int32_t k_min, k_max;        /* candidate peak counts, 1 <= k_min <= k_max */
     uint32_t uid;                /* identity of the spectrum; part of the random-number key */
     double noise_s[3];           /* s0, s1, s2 >= 0 of the heteroscedastic noise (ignored otherwise) */

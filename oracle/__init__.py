@@ -20,8 +20,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-PEAK = {"gauss": 0, "pvoigt": 1}
-BG = {"none": 0, "const": 1, "linear": 2, "shirley": 3}
+PEAK = {"gauss": 0, "pvoigt": 1, "xrd": 2}
+BG = {"none": 0, "const": 1, "linear": 2, "shirley": 3, "xrd": 4}
 NOISE = {"gauss": 0, "poisson": 1, "hetero": 2}
 PRIOR = {"uniform": 0, "gamma": 1, "normal": 2, "fixed": 3}
 
@@ -39,10 +39,11 @@ class _Problem(ctypes.Structure):
         ("bg_kind", ctypes.c_int32),
         ("noise_kind", ctypes.c_int32),
         ("sigma", ctypes.c_double),
-        ("peak_prior", _Prior * 4),
-        ("bg_prior", _Prior * 2),
+        ("peak_prior", _Prior * 9),
+        ("bg_prior", _Prior * 4),
         ("peak_prior_k", ctypes.POINTER(_Prior)),
         ("noise_s", ctypes.c_double * 3),
+        ("mu_ref", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -95,6 +96,8 @@ def lib():
             "or_dim": (I32, [PP, I32]),
             "or_peak_gauss": (D, [D, D, D, D]),
             "or_peak_pv": (D, [D, D, D, D, D]),
+            "or_xrd_pv": (D, [D, D, D, D, D]),
+            "or_peak_xrd": (D, [D, D, PD]),
             "or_forward": (D, [PP, I32, PD, D]),
             "or_peaks": (D, [PP, I32, PD, D]),
             "or_shirley": (None, [PD, PD, I32, D, D, PD]),
@@ -150,22 +153,26 @@ class Problem:
         pr.bg_kind = BG[spec.bg_kind]
         pr.noise_kind = NOISE[spec.noise_kind]
         pr.sigma = float(spec.sigma)
-        for q in range(4):
+        for q in range(9):
             pr.peak_prior[q] = _prior(spec.peak_prior[q]) if q < len(spec.peak_prior) else _Prior(3, 0.0, 0.0)
-        for q in range(2):
+        for q in range(4):
             pr.bg_prior[q] = _prior(spec.bg_prior[q]) if q < len(spec.bg_prior) else _Prior(3, 0.0, 0.0)
         self._pk = None
         pk = getattr(spec, "peak_prior_k", None)
         if pk is not None:
             rows = []
             for row in pk:
-                rr = list(row) + [("fixed", 0.0, 0.0)] * (4 - len(row))
+                rr = list(row) + [("fixed", 0.0, 0.0)] * (9 - len(row))
                 rows.extend(_prior(p) for p in rr)
             self._pk = (_Prior * len(rows))(*rows)
             pr.peak_prior_k = ctypes.cast(self._pk, ctypes.POINTER(_Prior))
         ns = getattr(spec, "noise_s", None) or (0.0, 0.0, 0.0)
         for q in range(3):
             pr.noise_s[q] = float(ns[q])
+        mr = getattr(spec, "mu_ref", None)
+        self._mu_ref = None if mr is None else np.ascontiguousarray(mr, dtype=np.float64)
+        if self._mu_ref is not None:
+            pr.mu_ref = _pd(self._mu_ref)
         self.c = pr
 
     @property
@@ -198,6 +205,15 @@ def box_muller(r0: int, r1: int) -> float:
 
 def peak_gauss(x, A, mu, b) -> float:
     return lib().or_peak_gauss(x, A, mu, b)
+
+
+def xrd_pv(x, rho, Sigma, Omega, r) -> float:
+    return lib().or_xrd_pv(float(x), float(rho), float(Sigma), float(Omega), float(r))
+
+
+def peak_xrd(x, mu_ref, t) -> float:
+    tt = np.ascontiguousarray(t, dtype=np.float64)
+    return lib().or_peak_xrd(float(x), float(mu_ref), _pd(tt))
 
 
 def peak_pv(x, A, mu, sigma, eta) -> float:

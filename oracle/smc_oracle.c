@@ -103,8 +103,11 @@ double or_box_muller(uint32_t r0, uint32_t r1)
  * maximum, eta the Gaussian fraction.
  * Background: none; constant (b); linear (c0, c1) -> c0 + c1*x.
  * ------------------------------------------------------------------------ */
-int or_params_per_peak(int peak_kind) { return peak_kind == OR_PEAK_GAUSS ? 3 : 4; }
-int or_params_bg(int bg_kind) { return bg_kind == OR_BG_NONE ? 0 : (bg_kind == OR_BG_CONST ? 1 : 2); }
+int or_params_per_peak(int peak_kind) { return peak_kind == OR_PEAK_GAUSS ? 3 : (peak_kind == OR_PEAK_PVOIGT ? 4 : 9); }
+int or_params_bg(int bg_kind)
+{
+    return bg_kind == OR_BG_NONE ? 0 : (bg_kind == OR_BG_CONST ? 1 : (bg_kind == OR_BG_XRD ? 4 : 2));
+}
 /* (The Shirley background of App. D has two parameters too: the intensities a at the first
  * and b at the last data point.) */
 int or_dim(const or_problem* p, int K) { return K * or_params_per_peak(p->peak_kind) + or_params_bg(p->bg_kind); }
@@ -115,7 +118,7 @@ or_prior or_component_prior(const or_problem* p, int K, int j)
     int np = or_params_per_peak(p->peak_kind);
     if (j < K * np) {
         int k = j / np, q = j % np;
-        if (p->peak_prior_k) return p->peak_prior_k[k * 4 + q];
+        if (p->peak_prior_k) return p->peak_prior_k[k * 9 + q];
         return p->peak_prior[q];
     }
     return p->bg_prior[j - K * np];
@@ -139,6 +142,37 @@ double or_peak_pv(double x, double A, double mu, double sigma, double eta)
     return A * (eta * gauss + (1.0 - eta) * lorentz);
 }
 
+/* XRD pseudo-Voigt, Eqs. (xrd_pvoigt, xrd_gauss, xrd_lorentz): (1 - r) G + r L with
+ * G = exp(-4 ln2 ((x - rho)/Sigma)^2) and L = 1 / (1 + 4 ((x - rho)/Omega)^2), Sigma and Omega
+ * full widths at half maximum. */
+double or_xrd_pv(double x, double rho, double Sigma, double Omega, double r)
+{
+    double zg = (x - rho) / Sigma, zl = (x - rho) / Omega;
+    double G = exp(-4.0 * log(2.0) * zg * zg);
+    double L = 1.0 / (1.0 + 4.0 * zl * zl);
+    return (1.0 - r) * G + r * L;
+}
+
+/* One XRD peak, Eq. (xrd_forward_model) with Eqs. (xrd_sigma, xrd_omega, xrd_asym): the
+ * parameters t = (A, shift, r, alpha, u, v, w, s, tl), position mu = mu_ref + shift, widths
+ * Sigma(x) = a sqrt(u tan^2(x/2) - v tan(x/2) + w) and Omega(x) = a (s / cos(x/2) + tl tan(x/2)),
+ * a = alpha for x >= mu and 1 below, x/2 converted from degrees to radians.  NaN where the
+ * Caglioti argument is not positive (the width is undefined). */
+double or_peak_xrd(double x, double mu_ref, const double* t)
+{
+    const double pi = 3.141592653589793238462643383279502884;
+    double A = t[0], mu = mu_ref + t[1], r = t[2], alpha = t[3];
+    double u = t[4], v = t[5], w = t[6], s = t[7], tl = t[8];
+    double h = 0.5 * x * pi / 180.0;
+    double tn = tan(h), sc = 1.0 / cos(h);
+    double asym = x >= mu ? alpha : 1.0;
+    double c = u * tn * tn - v * tn + w;
+    if (!(c > 0.0)) return NAN;
+    double Sigma = asym * sqrt(c);
+    double Omega = asym * (s * sc + tl * tn);
+    return A * or_xrd_pv(x, mu, Sigma, Omega, r);
+}
+
 /* Sum of the K basis functions at x. */
 double or_peaks(const or_problem* p, int K, const double* theta, double x)
 {
@@ -147,7 +181,8 @@ double or_peaks(const or_problem* p, int K, const double* theta, double x)
     for (int k = 0; k < K; ++k) {
         const double* t = theta + k * np;
         if (p->peak_kind == OR_PEAK_GAUSS) f += or_peak_gauss(x, t[0], t[1], t[2]);
-        else f += or_peak_pv(x, t[0], t[1], t[2], t[3]);
+        else if (p->peak_kind == OR_PEAK_PVOIGT) f += or_peak_pv(x, t[0], t[1], t[2], t[3]);
+        else f += or_peak_xrd(x, p->mu_ref ? p->mu_ref[k] : 0.0, t);
     }
     return f;
 }
@@ -161,6 +196,7 @@ double or_forward(const or_problem* p, int K, const double* theta, double x)
     if (p->bg_kind == OR_BG_CONST) f += bg[0];
     else if (p->bg_kind == OR_BG_LINEAR) f += bg[0] + bg[1] * x;
     else if (p->bg_kind == OR_BG_SHIRLEY) f = NAN;
+    else if (p->bg_kind == OR_BG_XRD) f += bg[0] * or_xrd_pv(x, 0.0, bg[1], bg[1], bg[2]) + bg[3];
     return f;
 }
 
@@ -257,7 +293,7 @@ double or_energy(const or_problem* p, int K, const double* theta)
     } else {
         for (int i = 0; i < p->n; ++i) {
             double f = or_forward(p, K, theta, p->x[i]);
-            if (!(f > 0.0)) return INFINITY;
+            if (!(f > 0.0)) return INFINITY;   /* also NaN: a width undefined at this point */
             e += f - p->y[i] * log(f) + lgamma(p->y[i] + 1.0);
         }
     }

@@ -7,8 +7,8 @@
 #define SMC_ORACLE_H
 #include <stdint.h>
 
-enum { OR_PEAK_GAUSS = 0, OR_PEAK_PVOIGT = 1 };
-enum { OR_BG_NONE = 0, OR_BG_CONST = 1, OR_BG_LINEAR = 2, OR_BG_SHIRLEY = 3 };
+enum { OR_PEAK_GAUSS = 0, OR_PEAK_PVOIGT = 1, OR_PEAK_XRD = 2 };
+enum { OR_BG_NONE = 0, OR_BG_CONST = 1, OR_BG_LINEAR = 2, OR_BG_SHIRLEY = 3, OR_BG_XRD = 4 };
 enum { OR_NOISE_GAUSS = 0, OR_NOISE_POISSON = 1, OR_NOISE_HETERO = 2 };
 enum { OR_PRIOR_UNIFORM = 0, OR_PRIOR_GAMMA = 1, OR_PRIOR_NORMAL = 2, OR_PRIOR_FIXED = 3 };
 
@@ -24,10 +24,11 @@ typedef struct {
     const double* y;
     int32_t peak_kind, bg_kind, noise_kind;
     double sigma;
-    or_prior peak_prior[4];
-    or_prior bg_prior[2];
-    const or_prior* peak_prior_k; /* optional [k][4] per-peak priors, NULL = peak_prior for all */
+    or_prior peak_prior[9];       /* per peak parameter (up to 9: the XRD peak) */
+    or_prior bg_prior[4];         /* per background parameter (up to 4: the XRD background) */
+    const or_prior* peak_prior_k; /* optional [k][9] per-peak priors, NULL = peak_prior for all */
     double noise_s[3];            /* heteroscedastic noise: sigma0, sigma1, sigma2 */
+    const double* mu_ref;         /* XRD peaks: reference positions [k_max] (degrees 2theta) */
 } or_problem;
 
 typedef struct {
@@ -55,6 +56,8 @@ int or_dim(const or_problem* p, int K);
 or_prior or_component_prior(const or_problem* p, int K, int j);
 double or_peak_gauss(double x, double A, double mu, double b);
 double or_peak_pv(double x, double A, double mu, double sigma, double eta);
+double or_xrd_pv(double x, double rho, double Sigma, double Omega, double r);
+double or_peak_xrd(double x, double mu_ref, const double* t);
 double or_peaks(const or_problem* p, int K, const double* theta, double x);
 double or_forward(const or_problem* p, int K, const double* theta, double x);
 void or_shirley(const double* x, const double* peaks, int n, double a, double b, double* B);

@@ -56,7 +56,7 @@ smc_prior component_prior(const smc_problem& p, int K, int j) {
     const int np = params_per_peak(p.peak_kind);
     if (j < K * np) {
         const int k = j / np, q = j % np;
-        return p.peak_prior_k ? p.peak_prior_k[k * 4 + q] : p.peak_prior[q];
+        return p.peak_prior_k ? p.peak_prior_k[k * SMC_MAX_PEAK_PARAMS + q] : p.peak_prior[q];
     }
     return p.bg_prior[j - K * np];
 }
@@ -93,7 +93,7 @@ smc_status validate(const smc_problem* p, const smc_options* o) {
     if (p->peak_prior_k)
         for (int k = 0; k < p->k_max; ++k)
             for (int q = 0; q < np; ++q)
-                if (!prior_ok(p->peak_prior_k[k * 4 + q])) return SMC_EINVAL;
+                if (!prior_ok(p->peak_prior_k[k * SMC_MAX_PEAK_PARAMS + q])) return SMC_EINVAL;
     for (int q = 0; q < params_bg(p->bg_kind); ++q)
         if (!prior_ok(p->bg_prior[q])) return SMC_EINVAL;
     if (o->n_particles < 2 || o->n_moves < 1) return SMC_EINVAL;
@@ -425,7 +425,7 @@ void Spectrum::assign(const smc_problem& p) {
     prob.x = x.data();
     prob.y = y.data();
     if (p.peak_prior_k) {
-        ppk.assign(p.peak_prior_k, p.peak_prior_k + 4 * p.k_max);
+        ppk.assign(p.peak_prior_k, p.peak_prior_k + SMC_MAX_PEAK_PARAMS * p.k_max);
         prob.peak_prior_k = ppk.data();
     } else {
         ppk.clear();

@@ -43,8 +43,8 @@ class smc_problem(ctypes.Structure):
         ("bg_kind", ctypes.c_int32),
         ("noise_kind", ctypes.c_int32),
         ("sigma", ctypes.c_double),
-        ("peak_prior", smc_prior * 4),
-        ("bg_prior", smc_prior * 2),
+        ("peak_prior", smc_prior * 9),
+        ("bg_prior", smc_prior * 4),
         ("peak_prior_k", ctypes.POINTER(smc_prior)),
         ("k_min", ctypes.c_int32),
         ("k_max", ctypes.c_int32),
@@ -176,16 +176,16 @@ class Problem:
         p.bg_kind = BG[spec.bg_kind]
         p.noise_kind = NOISE[spec.noise_kind]
         p.sigma = float(spec.sigma)
-        for q in range(4):
+        for q in range(9):
             p.peak_prior[q] = _prior(spec.peak_prior[q]) if q < len(spec.peak_prior) else smc_prior(3, 0.0, 0.0)
-        for q in range(2):
+        for q in range(4):
             p.bg_prior[q] = _prior(spec.bg_prior[q]) if q < len(spec.bg_prior) else smc_prior(3, 0.0, 0.0)
         self._pk = None
         pk = getattr(spec, "peak_prior_k", None)
         if pk is not None:
             rows = []
             for row in pk:
-                rows.extend(_prior(x) for x in list(row) + [("fixed", 0.0, 0.0)] * (4 - len(row)))
+                rows.extend(_prior(x) for x in list(row) + [("fixed", 0.0, 0.0)] * (9 - len(row)))
             self._pk = (smc_prior * len(rows))(*rows)
             p.peak_prior_k = ctypes.cast(self._pk, P(smc_prior))
         p.k_min = int(spec.k_min if k_min is None else k_min)

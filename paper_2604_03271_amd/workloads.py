@@ -28,7 +28,9 @@ class Spectrum:
     x: np.ndarray
     y: np.ndarray
     peak_kind: str                    # "gauss" (A, mu, b=precision) | "pvoigt" (A, mu, sigma=HWHM, eta=Gaussian fraction)
+                                      # | "xrd" (A, shift, r, alpha, u, v, w, s, t at reference positions mu_ref)
     bg_kind: str                      # "none" | "const" (b) | "linear" (c0, c1) | "shirley" (a, b)
+                                      # | "xrd" (a, sigma_bg, r_bg, b)
     noise_kind: str                   # "gauss" (known sigma) | "poisson" | "hetero" (noise_s)
     sigma: float
     peak_prior: Sequence[Prior]
@@ -39,6 +41,7 @@ class Spectrum:
     truth: Optional[dict] = None
     uid: int = 0
     noise_s: Optional[Tuple[float, float, float]] = None   # heteroscedastic noise (s0, s1, s2)
+    mu_ref: Optional[List[float]] = None   # XRD peaks: reference positions, one per candidate peak
 
     @property
     def n(self) -> int:
@@ -316,4 +319,64 @@ def xps_shirley(index: int = 0, n: int = 840, k_min: int = 6, k_max: int = 8) ->
     sp = Spectrum(x, y, "pvoigt", "shirley", "hetero", 0.0, pp, bgp, k_min, k_max,
                   truth={"K": 7, "peaks": peaks, "bg": (a, b)}, uid=7000 + index)
     sp.noise_s = XPS_NOISE
+    return sp
+
+
+# --- XRD powder patterns (App. C, App. E: the model of Eq. xrd_forward_model) ---------------
+# Table xrd_true_phase gives the phase parameters of the paper's artificial data (rutile,
+# anatase, brookite) and table xrd_true_bg its background; the crystallographic reference
+# positions are not printed, so the main reflections of the three TiO2 phases for Cu K-alpha
+# radiation are used (rutile (110), anatase (101), brookite (121)), one peak per phase as the
+# model is written.  Poisson counts on a 2theta grid of 10-60 degrees.
+
+XRD_TRUE = {  # A, shift, r, alpha, u, v, w, s, t
+    "rutile": (10000.0, 0.035, 0.50, 0.6, 0.03, 0.03, 0.06, 0.06, 0.03),
+    "anatase": (3500.0, 0.055, 0.65, 0.9, 0.1, 0.1, 0.2, 0.2, 0.1),
+    "brookite": (1000.0, 0.04, 0.75, 1.0, 0.1, 0.1, 0.2, 0.2, 0.1),
+}
+XRD_MU_REF = {"rutile": 27.447, "anatase": 25.281, "brookite": 30.808}
+XRD_BG_TRUE = (60000.0, 10.0, 0.0, 100.0)   # a, sigma_bg, r_bg, b
+
+
+def _gen_xrd_pv(x, rho, Sig, Om, r):
+    G = np.exp(-4.0 * np.log(2.0) * ((x - rho) / Sig) ** 2)
+    L = 1.0 / (1.0 + 4.0 * ((x - rho) / Om) ** 2)
+    return (1.0 - r) * G + r * L
+
+
+def _gen_xrd_peak(x, mu_ref, t):
+    A, sh, r, al, u, v, w, s, tl = t
+    mu = mu_ref + sh
+    h = np.radians(0.5 * x)
+    tn, sc = np.tan(h), 1.0 / np.cos(h)
+    a = np.where(x >= mu, al, 1.0)
+    Sig = a * np.sqrt(u * tn ** 2 - v * tn + w)
+    Om = a * (s * sc + tl * tn)
+    return A * _gen_xrd_pv(x, mu, Sig, Om, r)
+
+
+def xrd_priors(y, K):
+    ymax, ymin = float(np.max(y)), float(np.min(y))
+    peak = [("gamma", 4.0, 4.0 / (ymax - ymin)), ("normal", 0.0, 0.05), ("uniform", 0.0, 1.0), ("gamma", 5.0, 4.0),
+            ("gamma", 1.0, 10.0), ("gamma", 1.0, 10.0), ("gamma", 2.0, 20.0), ("gamma", 2.0, 20.0),
+            ("gamma", 1.0, 10.0)]
+    bg = [("gamma", 2.0, 1.0 / ymax), ("gamma", 2.0, 0.4), ("uniform", 0.0, 1.0),
+          ("uniform", ymin - float(np.sqrt(ymin)), ymin + float(np.sqrt(ymin)))]
+    return peak, bg
+
+
+def xrd_powder(n: int = 1000, index: int = 0) -> Spectrum:
+    """The paper's artificial XRD pattern (three TiO2 phases, pseudo-Voigt background), N points on
+    2theta in [10, 60], Poisson counts; the free energy at K = 3."""
+    rng = np.random.default_rng(1000 * 8 + index)
+    x = f32(10.0 + 50.0 * np.arange(n) / (n - 1))
+    f = np.full(n, XRD_BG_TRUE[3]) + XRD_BG_TRUE[0] * _gen_xrd_pv(x, 0.0, XRD_BG_TRUE[1], XRD_BG_TRUE[1], XRD_BG_TRUE[2])
+    names = ["rutile", "anatase", "brookite"]
+    for nm in names:
+        f = f + _gen_xrd_peak(x, XRD_MU_REF[nm], XRD_TRUE[nm])
+    y = rng.poisson(f).astype(np.float64)
+    pp, bgp = xrd_priors(y, 3)
+    sp = Spectrum(x, y, "xrd", "xrd", "poisson", 0.0, pp, bgp, 3, 3,
+                  truth={"K": 3, "peaks": [XRD_TRUE[nm] for nm in names], "bg": XRD_BG_TRUE}, uid=8000 + index)
+    sp.mu_ref = [XRD_MU_REF[nm] for nm in names]
     return sp
