@@ -18,6 +18,9 @@ the prior's support) covers N points.
 spectra instead (App. B: N = 300 / 1000 / 3000, n = 10 / 10 / 100 moves per
 temperature, free energy at the true K only), by default at the largest
 particle counts the paper runs (10^6, and 3 x 10^6 for K = 30).
+--workload xrd-1000 | xrd-5000 times the paper's artificial XRD pattern (App. E:
+three TiO2 phases at reference positions, pseudo-Voigt background, Poisson
+counts, N points on 2theta 10-60 degrees), free energy at K = 3, n = 10.
 
 Prints one JSON line.
 """
@@ -51,6 +54,19 @@ LINEAR_VALU = 2
 # (a background proposal's cost, the cheapest kind), a lower bound.
 XPS_SHAPE = (19, 4)
 XPS_LINEAR = (8, 2)
+# XRD powder profile (Poisson counts), per point.  Every proposal forms the term's value
+# on the rest of the model (2 fma) and the Poisson term f - y ln f into the sum (fma, add
+# and log2): 4 VALU + 1 transcendental, all a linear proposal (A, r; a, r_bg, b) needs,
+# from the cached shapes.  A peak shape proposal (shift, alpha, u, v, w, s, t) first forms
+# x - mu and its square (2), the asymmetry select (2), the Caglioti polynomial (2), a^2 c
+# (2), 1 + tan^2 (1), t tan + s sec and the a factor (3), -4 d^2 / Sigma^2 (2), Omega^2,
+# 4 d^2 and 1 + 4 d^2 / Omega^2 (3): 17 VALU + sqrt, rcp, exp2, rcp, rcp.  The
+# background's width proposal forms 4 x^2 / sigma_bg^2 (3) and 1 + z (1), exp2 and rcp.
+# Every sweep proposes each component once, so of the 7 K + 1 shape proposals per sweep
+# one is the background's.
+XRD_PEAK_SHAPE = (21, 6)
+XRD_BG_SHAPE = (8, 3)
+XRD_LINEAR = (4, 1)
 # Issue cost of one transcendental relative to one VALU instruction on gfx950,
 # measured with a throughput microbenchmark (see the design notes).
 TRANS_COST = float(os.environ.get("SMC_TRANS_COST", "2.0"))
@@ -197,6 +213,12 @@ def _workload(name, native_options, workloads, particles):
         P, n = particles or 2_000_000, 100
         desc = (f"XPS-like stand-in N={spec.n}, pseudo-Voigt peaks on a dynamic Shirley background, "
                 f"heteroscedastic noise, K={spec.k_min}..{spec.k_max}, P={P} per K, waste-free n={n}")
+    elif name.startswith("xrd-"):
+        N = int(name.split("-")[1])
+        spec = workloads.xrd_powder(n=N, index=0)
+        P, n = particles or 262144, 10
+        desc = (f"paper XRD artificial pattern N={N} (2theta 10-60, three TiO2 phases, Poisson counts), "
+                f"free energy at K=3 (31 parameters), P={P}, waste-free n={n}")
     else:
         K = int(name.split("-k")[1])
         spec = workloads.paper_gaussian(K)
@@ -213,7 +235,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="xps-pv",
-                    choices=["xps-pv", "paper-k3", "paper-k10", "paper-k30", "xps-shirley"])
+                    choices=["xps-pv", "paper-k3", "paper-k10", "paper-k30", "xps-shirley", "xrd-1000",
+                             "xrd-5000"])
     ap.add_argument("--particles", type=int, default=0, help="particles per K (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -272,9 +295,16 @@ def main():
     # roofline of the dominant kernel (the MH move): algorithmic lane-instruction slots per
     # launch over the launch's average duration from HIP events on the library's stream
     assert kinds["stage0"] + kinds["shape"] + kinds["linear"] == evals
+    K_top = spec.k_max
     if spec.noise_kind == "hetero":
         shape_slots = XPS_SHAPE[0] + TRANS_COST * XPS_SHAPE[1]
         linear_slots = XPS_LINEAR[0] + TRANS_COST * XPS_LINEAR[1]
+    elif spec.peak_kind == "xrd":
+        assert spec.k_min == spec.k_max   # the bg share of shape proposals below is per K
+        fb = 1.0 / (7 * K_top + 1)
+        shape_slots = ((1 - fb) * (XRD_PEAK_SHAPE[0] + TRANS_COST * XRD_PEAK_SHAPE[1])
+                       + fb * (XRD_BG_SHAPE[0] + TRANS_COST * XRD_BG_SHAPE[1]))
+        linear_slots = XRD_LINEAR[0] + TRANS_COST * XRD_LINEAR[1]
     else:
         shape_slots = SHAPE_VALU[spec.peak_kind] + TRANS_COST * SHAPE_TRANS[spec.peak_kind]
         linear_slots = LINEAR_VALU

@@ -62,8 +62,8 @@ typedef int32_t smc_status;
 #define SMC_EBUDGET (-6)  /* a served request can never fit the memory budget */
 #define SMC_EAGAIN (-7)   /* server queue full / nothing ready yet */
 
-enum { SMC_PEAK_GAUSS = 0, SMC_PEAK_PVOIGT = 1 };
-enum { SMC_BG_NONE = 0, SMC_BG_CONST = 1, SMC_BG_LINEAR = 2, SMC_BG_SHIRLEY = 3 };
+enum { SMC_PEAK_GAUSS = 0, SMC_PEAK_PVOIGT = 1, SMC_PEAK_XRD = 2 };
+enum { SMC_BG_NONE = 0, SMC_BG_CONST = 1, SMC_BG_LINEAR = 2, SMC_BG_SHIRLEY = 3, SMC_BG_XRD = 4 };
 enum { SMC_NOISE_GAUSS = 0, SMC_NOISE_POISSON = 1, SMC_NOISE_HETERO = 2 };
 enum { SMC_PRIOR_UNIFORM = 0, SMC_PRIOR_GAMMA = 1, SMC_PRIOR_NORMAL = 2, SMC_PRIOR_FIXED = 3 };
 
@@ -87,7 +87,14 @@ typedef struct {
  * with known sigma, Poisson counts (Eq. xrd_poisson), or heteroscedastic Gaussian with
  * sigma_i^2 = s0^2 f_i + s1^2 f_i^2 + s2^2 (App. D).  The Shirley background and the
  * heteroscedastic noise go together, with pseudo-Voigt peaks and N <= 1024 (the XPS model
- * form of App. D); other combinations of these two are SMC_EINVAL. */
+ * form of App. D); other combinations of these two are SMC_EINVAL.
+ * The XRD powder profile of App. E: peaks (A, shift, r, alpha, u, v, w, s, t) at reference
+ * positions mu_ref (position = mu_ref + shift; Caglioti Gaussian width, sec/tan Lorentzian
+ * width, asymmetry alpha above the position; x in degrees 2theta, 0 < x < 180) with the
+ * pseudo-Voigt background (a, sigma_bg, r_bg, b) and Poisson counts, N <= 5120; XRD peaks and
+ * the XRD background go together.  A parameter vector whose squared Caglioti width is not
+ * positive, or whose Lorentzian width is zero, has no defined model and gets energy +inf
+ * (it is never accepted). */
 typedef struct {
     int32_t n_points;            /* N >= 1 */
     const double* x;             /* (host) [N]; copied at init and rounded to FP32 */
@@ -102,6 +109,7 @@ typedef struct {
     int32_t k_min, k_max;        /* candidate peak counts, 1 <= k_min <= k_max */
     uint32_t uid;                /* identity of the spectrum; part of the random-number key */
     double noise_s[3];           /* s0, s1, s2 >= 0 of the heteroscedastic noise (ignored otherwise) */
+    const double* mu_ref;        /* (host) XRD peaks: reference positions [k_max]; NULL otherwise */
 } smc_problem;
 
 typedef struct {
@@ -188,10 +196,12 @@ smc_status smc_particles(const smc_ctx* ctx, int32_t K, float* theta_soa, float*
  * A credible interval at level c is (q_{(1-c)/2}, q_{(1+c)/2}): probs {0.025, 0.975} give the
  * 95% interval, {0.005, 0.995} the 99% one.  relabel != 0 first sorts every particle's peaks
  * by centre (stable), since the prior is exchangeable in the peaks and per-peak summaries
- * need one labelling; the stored particles are not changed.  mean [d] and quant
+ * need one labelling; the stored particles are not changed.  XRD problems take relabel = 0:
+ * their peak k belongs to the reference position mu_ref[k].  mean [d] and quant
  * [n_probs * d] are host arrays.  Allocates and frees a device buffer of d * P floats when
  * relabel != 0.  Errors: SMC_EINVAL (bad K, probabilities outside [0, 1], n_probs out of
- * range, NULL outputs), SMC_ESTATE (K has not reached beta = 1), SMC_EDEVICE. */
+ * range, NULL outputs, relabel != 0 on an XRD problem), SMC_ESTATE (K has not reached
+ * beta = 1), SMC_EDEVICE. */
 smc_status smc_posterior_summary(smc_ctx* ctx, int32_t K, const double* probs, int32_t n_probs, int32_t relabel,
                                  double* mean, double* quant);
 

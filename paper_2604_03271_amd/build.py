@@ -18,7 +18,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-I" + os.path.join(ROOT, "include"),
          "-I" + CSRC, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-pass-failed"]
-SOURCES = ["kernels_00.hip", "kernels_01.hip", "kernels_10.hip", "kernels_11.hip", "kernels_xps.hip", "stage.hip",
+SOURCES = ["kernels_00.hip", "kernels_01.hip", "kernels_10.hip", "kernels_11.hip", "kernels_xps.hip", "kernels_xrd.hip",
+           "stage.hip",
            "summary.hip", "smc_host.cpp", "hooks.cpp", "batch.cpp"]
 
 

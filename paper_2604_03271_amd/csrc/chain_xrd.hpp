@@ -1,0 +1,341 @@
+// chain_xrd.hpp -- likelihood and Metropolis-Hastings kernels of the XRD powder
+// profile of App. E (Eqs. xrd_forward_model, xrd_pvoigt, xrd_gauss, xrd_lorentz,
+// xrd_sigma, xrd_omega, xrd_asym, xrd_bg) with Poisson counts (Eq. xrd_poisson).
+//
+// Peak k has nine parameters (A, shift, r, alpha, u, v, w, s, t) at the reference
+// position mu_ref[k]: mu = mu_ref + shift, and at point x (degrees 2theta)
+//   Sigma^2 = a^2 (u tan^2(x/2) - v tan(x/2) + w),  Omega = a (s sec(x/2) + t tan(x/2)),
+// a = alpha for x >= mu and 1 below; G = exp(-4 ln2 (x - mu)^2 / Sigma^2) and
+// L = 1 / (1 + 4 (x - mu)^2 / Omega^2); value A ((1 - r) G + r L).  The background
+// (a, sigma_bg, r_bg, b) is a ((1 - r_bg) G_bg + r_bg L_bg) + b with both widths sigma_bg
+// at position 0.  Layout and residual cache as in chain.hpp (lane r owns points r,
+// r + LC, ...; D = model without the current term), plus tan(x/2) per point
+// (sec(x/2) = sqrt(1 + tan^2(x/2)) for 0 < x < 180 degrees, formed when needed).
+// The current term's shapes G, L are cached: a proposal of A or r (or of the
+// background's a, r_bg, b) only forms the deviance from them; a proposal of a shift,
+// asymmetry or width parameter (or sigma_bg) re-evaluates them.  Where a Caglioti
+// argument is not positive the width is undefined and the energy is +inf.
+#pragma once
+
+#include "chain.hpp"
+
+namespace smc {
+
+struct XrdC {
+    float mu, alpha, u, v, w, s, t;  // shape (peak); bg: mu = 0 and s = 1 / sigma_bg^2
+    float aG, aL, c0;                // value = aG G + aL L + c0
+};
+
+// Constants of peak k (th: its nine parameters) at reference position mref.
+__device__ __forceinline__ XrdC xrd_peak_consts(const float* th, float mref) {
+    XrdC q;
+    q.mu = mref + th[1];
+    q.alpha = th[3];
+    q.u = th[4];
+    q.v = th[5];
+    q.w = th[6];
+    q.s = th[7];
+    q.t = th[8];
+    q.aG = th[0] * (1.0f - th[2]);
+    q.aL = th[0] * th[2];
+    q.c0 = 0.0f;
+    return q;
+}
+
+__device__ __forceinline__ XrdC xrd_bg_consts(const float* th) {
+    XrdC q{};
+    q.mu = 0.0f;
+    q.s = __builtin_amdgcn_rcpf(th[1] * th[1]);
+    q.aG = th[0] * (1.0f - th[2]);
+    q.aL = th[0] * th[2];
+    q.c0 = th[3];
+    return q;
+}
+
+// Components of a peak that enter its value linearly (A, r) and of the background (a, r_bg, b).
+__device__ __forceinline__ bool xrd_linear(bool is_bg, int q) { return is_bg ? q != 1 : (q == 0 || q == 2); }
+
+template <int L, int WPC, int PPL>
+struct XrdChain {
+    static constexpr int LC = L * WPC;
+    float x[PPL], tn[PPL], y[PPL];
+    float D[PPL];
+    float S1[PPL], S2[PPL];
+
+    __device__ __forceinline__ void load_points(const GroupDesc& g, int lane) {
+        constexpr float kHalfRad = 3.14159265358979f / 360.0f;
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            const int i = lane + p * LC;
+            const bool ok = i < g.n;
+            x[p] = ok ? g.x[i] : kFarX;
+            y[p] = ok ? g.y[i] : -1.0f;
+            tn[p] = tanf(ok ? g.x[i] * kHalfRad : 0.0f);
+        }
+    }
+
+    // Shapes of a peak at point p; `bad` collects undefined widths.
+    __device__ __forceinline__ void peak_shape(const XrdC& q, int p, float& e, float& l, bool& bad) const {
+        const float d = x[p] - q.mu;
+        const float d2 = d * d;
+        const float a = x[p] >= q.mu ? q.alpha : 1.0f;
+        const float c = __builtin_fmaf(__builtin_fmaf(q.u, tn[p], -q.v), tn[p], q.w);
+        bad |= !(c > 0.0f);
+        const float sig2 = a * a * c;
+        // sec(x/2) from an opaque copy of tan(x/2): hoisted out of the sweep loop it would
+        // cost PPL more live registers
+        float tv = tn[p];
+        asm volatile("" : "+v"(tv));
+        const float sec = __builtin_sqrtf(__builtin_fmaf(tv, tv, 1.0f));
+        const float om = a * __builtin_fmaf(q.s, sec, q.t * tn[p]);
+        e = __builtin_amdgcn_exp2f(-4.0f * d2 * __builtin_amdgcn_rcpf(sig2));
+        l = __builtin_amdgcn_rcpf(__builtin_fmaf(4.0f * d2, __builtin_amdgcn_rcpf(om * om), 1.0f));
+    }
+
+    __device__ __forceinline__ void bg_shape(const XrdC& q, int p, float& e, float& l) const {
+        float xv = x[p];   // opaque copy: 4 x^2 hoisted out of the sweep loop costs PPL registers
+        asm volatile("" : "+v"(xv));
+        const float z = 4.0f * xv * xv * q.s;   // 4 x^2 / sigma_bg^2
+        e = __builtin_amdgcn_exp2f(-z);
+        l = __builtin_amdgcn_rcpf(1.0f + z);
+    }
+
+    __device__ __forceinline__ void shape(bool is_bg, const XrdC& q, int p, float& e, float& l, bool& bad) const {
+        if (is_bg) bg_shape(q, p, e, l);
+        else peak_shape(q, p, e, l, bad);
+    }
+
+    __device__ __forceinline__ static float value(const XrdC& q, float e, float l) {
+        return __builtin_fmaf(q.aL, l, __builtin_fmaf(q.aG, e, q.c0));
+    }
+
+    // Padding points (x = kFarX, y = -1) contribute 0: the deviance maps y < 0 to 0, and
+    // their shapes are never evaluated into anything but that term.
+    __device__ __forceinline__ float partial_cached(const XrdC& q) const {
+        float acc = 0.0f;
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) acc += poisson_dev(y[p], D[p] + value(q, S1[p], S2[p]));
+        return acc;
+    }
+
+    __device__ __forceinline__ float partial_shape(bool is_bg, const XrdC& q) const {
+        float acc = 0.0f;
+        bool bad = false;
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            float e, l;
+            shape(is_bg, q, p, e, l, bad);
+            acc += poisson_dev(y[p], D[p] + value(q, e, l));
+        }
+        return bad ? __builtin_inff() : acc;
+    }
+
+    __device__ __forceinline__ void set_shapes(bool is_bg, const XrdC& q) {
+        bool bad = false;
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) shape(is_bg, q, p, S1[p], S2[p], bad);
+    }
+
+    // Term k joins the fixed part of the model in D (from its cached shapes, or evaluated).
+    __device__ __forceinline__ void include_cached(const XrdC& q) {
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) D[p] += value(q, S1[p], S2[p]);
+    }
+
+    __device__ __forceinline__ bool include_eval(bool is_bg, const XrdC& q) {
+        bool bad = false;
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            float e, l;
+            shape(is_bg, q, p, e, l, bad);
+            D[p] += value(q, e, l);
+        }
+        return bad;
+    }
+
+    // Term k becomes current: its shapes cached and its value taken out of D.
+    __device__ __forceinline__ void exclude(bool is_bg, const XrdC& q) {
+        set_shapes(is_bg, q);
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) D[p] -= value(q, S1[p], S2[p]);
+    }
+
+    __device__ __forceinline__ static XrdC term_consts(const GroupDesc& g, const float* th, int k) {
+        return k < g.K ? xrd_peak_consts(th + k * g.np, g.mu_ref[k]) : xrd_bg_consts(th + g.K * g.np);
+    }
+
+    // Constants of term k with its component q replaced by vn (registers only: the chain's
+    // parameter vector in LDS is shared by all its lanes).
+    __device__ __forceinline__ static XrdC term_consts_with(const GroupDesc& g, const float* th, int k, int q,
+                                                            float vn) {
+        if (k < g.K) {
+            float t9[9];
+            const float* b = th + k * 9;
+#pragma unroll
+            for (int u = 0; u < 9; ++u) t9[u] = u == q ? vn : b[u];
+            return xrd_peak_consts(t9, g.mu_ref[k]);
+        }
+        float t4[4];
+        const float* b = th + g.K * 9;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) t4[u] = u == q ? vn : b[u];
+        return xrd_bg_consts(t4);
+    }
+
+    // Rebuild D and the shapes of term 0 from th; the lane's share of the energy (+inf where
+    // a width is undefined anywhere in the chain's points of this lane).
+    __device__ __forceinline__ float rebuild(const GroupDesc& g, const float* th) {
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) D[p] = 0.0f;
+        bool bad = false;
+        for (int k = g.K; k >= 1; --k) bad |= include_eval(k == g.K, term_consts(g, th, k));
+        const XrdC q0 = term_consts(g, th, 0);
+        float acc = 0.0f;
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            peak_shape(q0, p, S1[p], S2[p], bad);
+            acc += poisson_dev(y[p], D[p] + value(q0, S1[p], S2[p]));
+        }
+        return bad ? __builtin_inff() : acc;
+    }
+
+    __device__ __forceinline__ void transition(const GroupDesc& g, const float* th, int from, int to) {
+        include_cached(term_consts(g, th, from));
+        exclude(to == g.K, term_consts(g, th, to));
+    }
+};
+
+template <int L, int WPC, int PPL>
+__global__ void __launch_bounds__(256) k_energy_xrd(const GroupDesc* __restrict__ groups,
+                                                    const MoveWork* __restrict__ work) {
+    using CS = XrdChain<L, WPC, PPL>;
+    constexpr int LC = CS::LC;
+    const MoveWork w = work[xcd_block(blockIdx.x, gridDim.x, LC / 16)];
+    const GroupDesc& g = groups[w.group];
+    extern __shared__ float lds[];
+    const int slot = threadIdx.x / LC, lane = threadIdx.x % LC;
+    const int d = g.d;
+    float* th = lds + slot * d;
+    float* red = lds + (256 / LC) * d;
+    const bool active = slot < w.nchains;
+    const int i = w.chain0 + slot;
+    if (active)
+        for (int j = lane; j < d; j += LC) th[j] = g.theta[(size_t)j * g.P + i];
+    __syncthreads();
+    if (!active) return;
+    CS cs;
+    cs.load_points(g, lane);
+    int parity = 0;
+    const float e = chain_sum<L, WPC>(cs.rebuild(g, th), red, parity);
+    if (lane == 0) g.energy[i] = e;
+}
+
+constexpr int xrd_min_waves(int points) { return points <= 6 ? 4 : (points <= 10 ? 3 : 2); }
+
+template <int L, int WPC, int PPL>
+__global__ void __launch_bounds__(256, xrd_min_waves(PPL)) k_move_xrd(const GroupDesc* __restrict__ groups,
+                                                                       const MoveWork* __restrict__ work) {
+    using CS = XrdChain<L, WPC, PPL>;
+    constexpr int LC = CS::LC;
+    constexpr int CPW = 256 / LC;
+    const MoveWork w = work[xcd_block(blockIdx.x, gridDim.x, LC / 16)];
+    const GroupDesc& g = groups[w.group];
+    GroupState* st = g.st;
+    if (st->done) return;
+    const int d = g.d;
+
+    extern __shared__ float lds[];
+    const int slot = threadIdx.x / LC, lane = threadIdx.x % LC;
+    DevPrior* pri = reinterpret_cast<DevPrior*>(lds);
+    float* body = lds + 4 * d;
+    float* th = body + slot * 3 * d;
+    float* inc = th + d;
+    float* lnu = inc + d;
+    uint32_t* accc = reinterpret_cast<uint32_t*>(body + CPW * 3 * d);
+    float* red = body + CPW * 3 * d + d;
+    uint32_t* nevals = reinterpret_cast<uint32_t*>(red + 2 * WPC);
+
+    const bool active = slot < w.nchains;
+    const int m = w.chain0 + slot;
+    const int n = g.n_moves;
+    const float beta = static_cast<float>(st->beta);
+    const uint32_t stage = static_cast<uint32_t>(st->stage);
+    const uint32_t K = static_cast<uint32_t>(g.K);
+
+    for (int j = threadIdx.x; j < d; j += 256) {
+        accc[j] = 0u;
+        pri[j] = g.prior[j];
+    }
+    if (threadIdx.x < 2) nevals[threadIdx.x] = 0u;
+    uint32_t my_shape = 0, my_linear = 0;
+    float E = 0.0f;
+    if (active) {
+        for (int j = lane; j < d; j += LC) th[j] = g.start[(size_t)j * g.M + m];
+        E = g.start_e[m];
+    }
+    CS cs;
+    if (active) cs.load_points(g, lane);
+    const int kt = g.K + 1;
+    int parity = 0;
+
+    for (int t = 0; t < n; ++t) {
+        __syncthreads();
+        if (active) {
+            for (int j = lane; j < d; j += LC) {
+                const uint4 r = draw(g.key0, g.key1, (uint32_t)m, stage, (uint32_t)(t * d + j), K, kPurposeMove);
+                inc[j] = g.step[j] * box_muller(r.x, r.y);
+                lnu[j] = fast_ln(u01(r.z));
+            }
+        }
+        __syncthreads();
+        if (active) {
+            if (t % kRebuildEvery == 0) E = chain_sum<L, WPC>(cs.rebuild(g, th), red, parity);
+            else cs.transition(g, th, kt - 1, 0);
+            for (int k = 0; k < kt; ++k) {
+                const bool is_bg = k == g.K;
+                const int j0 = is_bg ? g.K * g.np : k * g.np;
+                const int nq = is_bg ? g.nbg : g.np;
+                if (k > 0) cs.transition(g, th, k - 1, k);
+                for (int q = 0; q < nq; ++q) {
+                    const int j = j0 + q;
+                    const DevPrior pr = pri[j];
+                    if (pr.kind == SMC_PRIOR_FIXED) continue;
+                    const float vo = th[j];
+                    const float vn = vo + inc[j];
+                    if (!prior_in_support(pr, vn)) continue;
+                    const XrdC qn = CS::term_consts_with(g, th, k, q, vn);
+                    const bool linear = xrd_linear(is_bg, q);
+                    const float part = linear ? cs.partial_cached(qn) : cs.partial_shape(is_bg, qn);
+                    if (linear) ++my_linear;
+                    else ++my_shape;
+                    const float En = chain_sum<L, WPC>(part, red, parity);
+                    const float log_alpha = -beta * (En - E) + prior_log_ratio(pr, vn, vo);
+                    if (lnu[j] < log_alpha) {
+                        E = En;
+                        if (!linear) cs.set_shapes(is_bg, qn);
+                        th[j] = vn;
+                        if (lane == 0) atomicAdd(&accc[j], 1u);
+                    }
+                }
+            }
+            const size_t out = g.waste_free ? (size_t)m * n + t : (size_t)m;
+            if (g.waste_free || t == n - 1) {
+                for (int j = lane; j < d; j += LC) g.theta[(size_t)j * g.P + out] = th[j];
+                if (lane == 0) g.energy[out] = E;
+            }
+        }
+    }
+    if (active && lane == 0) {
+        if (my_shape) atomicAdd(&nevals[0], my_shape);
+        if (my_linear) atomicAdd(&nevals[1], my_linear);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < d; j += 256)
+        if (accc[j]) atomicAdd(&g.acc[j], accc[j]);
+    if (threadIdx.x == 0 && (nevals[0] | nevals[1])) {
+        atomicAdd(&g.st->evals, static_cast<unsigned long long>(nevals[0]) + nevals[1]);
+        if (nevals[1]) atomicAdd(&g.st->evals_linear, static_cast<unsigned long long>(nevals[1]));
+    }
+}
+
+}  // namespace smc

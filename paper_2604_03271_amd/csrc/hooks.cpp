@@ -43,7 +43,7 @@ smc_status make_hook_group(HookGroup& h, const smc_problem* prob, int K, int P, 
     o.lanes_per_chain = lanes;
     o.seed = seed;
     o.max_stages = 1;
-    if (prob->peak_prior_k && K > prob->k_max) return SMC_EINVAL;
+    if ((prob->peak_prior_k || prob->mu_ref) && K > prob->k_max) return SMC_EINVAL;
     smc_problem p = *prob;
     p.k_min = p.k_max = K;
     smc_status st = validate(&p, &o);
@@ -61,7 +61,7 @@ smc_status make_hook_group(HookGroup& h, const smc_problem* prob, int K, int P, 
     const size_t bytes = 4 * 4096 + sizeof(MoveWork) * work.size() + sizeof(DevPrior) * std::max(d, 1) +
                          sizeof(double) * std::max(d, 1) + sizeof(float) * std::max(d, 1) * 2 +
                          2 * sizeof(float) * p.n_points + sizeof(unsigned long long) * std::max(P, 1) +
-                         sizeof(double) * kTraceCols + 8192;
+                         sizeof(double) * kTraceCols + sizeof(float) * std::max(K, 1) + 8192;
     if (hipMalloc(&h.scratch.mem, bytes) != hipSuccess) return SMC_ENOMEM;
     Arena a{h.scratch.mem, bytes, 0};
     h.d_group = static_cast<GroupDesc*>(a.take(sizeof(GroupDesc)));
@@ -73,11 +73,14 @@ smc_status make_hook_group(HookGroup& h, const smc_problem* prob, int K, int P, 
     double* lam = static_cast<double*>(a.take(sizeof(double) * std::max(d, 1)));
     unsigned long long* cdf = static_cast<unsigned long long*>(a.take(sizeof(unsigned long long) * std::max(P, 1)));
     double* trace = static_cast<double*>(a.take(sizeof(double) * kTraceCols));
+    float* dmu = h.sp.mref_f.empty() ? nullptr : static_cast<float*>(a.take(sizeof(float) * K));
     if (!h.d_group || !h.d_state || !h.d_work || !dx || !dy || !pri || !lam || !cdf || !trace) return SMC_ENOMEM;
+    if (!h.sp.mref_f.empty() && !dmu) return SMC_ENOMEM;
 
     GroupDesc& g = h.g;
     model_consts(p, K, g);
     g.x = dx;
+    g.mu_ref = dmu;
     g.y = dy;
     g.prior = pri;
     g.P = P;
@@ -102,6 +105,7 @@ smc_status make_hook_group(HookGroup& h, const smc_problem* prob, int K, int P, 
     if (hipMemcpyAsync(dx, h.sp.xf.data(), sizeof(float) * p.n_points, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(dy, h.sp.yf.data(), sizeof(float) * p.n_points, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(pri, hp.data(), sizeof(DevPrior) * std::max(d, 1), hipMemcpyHostToDevice, s) != hipSuccess ||
+        (dmu && hipMemcpyAsync(dmu, h.sp.mref_f.data(), sizeof(float) * K, hipMemcpyHostToDevice, s) != hipSuccess) ||
         hipMemcpyAsync(h.d_state, &gs, sizeof(GroupState), hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(h.d_work, work.data(), sizeof(MoveWork) * work.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)

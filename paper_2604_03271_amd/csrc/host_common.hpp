@@ -13,6 +13,7 @@ namespace smc {
 
 constexpr int kMaxK = 64;
 constexpr int kMaxXpsPoints = 1024;   // XPS model form: 64 lanes x 16 points
+constexpr int kMaxXrdPoints = 5120;   // XRD powder profile: 256 lanes x 20 points
 
 struct Tile {
     int lc, pi, lanes, ppl;
@@ -44,6 +45,8 @@ struct Spectrum {
     std::vector<double> x, y;
     std::vector<float> xf, yf;
     std::vector<smc_prior> ppk;
+    std::vector<double> mref;        // XRD reference positions
+    std::vector<float> mref_f;
     void assign(const smc_problem& p);
 };
 

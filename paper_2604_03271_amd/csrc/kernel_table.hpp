@@ -16,10 +16,11 @@ constexpr int kPplOf[kNumPpl] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24,
 
 // [peak kind][noise kind][lane configuration][points per lane]; noise kind 2 (heteroscedastic,
 // with the Shirley background) exists for pseudo-Voigt peaks, one-wavefront lane
-// configurations and at most 16 points per lane only (other entries are null).
+// configurations and at most 16 points per lane only; peak kind 2 (XRD) for Poisson counts
+// and at most 20 points per lane (other entries are null).
 struct KernelTable {
-    const void* move[2][3][kNumLaneCfg][kNumPpl];
-    const void* energy[2][3][kNumLaneCfg][kNumPpl];
+    const void* move[3][3][kNumLaneCfg][kNumPpl];
+    const void* energy[3][3][kNumLaneCfg][kNumPpl];
 };
 
 void register_kernels_00(KernelTable& t);
@@ -27,5 +28,6 @@ void register_kernels_01(KernelTable& t);
 void register_kernels_10(KernelTable& t);
 void register_kernels_11(KernelTable& t);
 void register_kernels_xps(KernelTable& t);
+void register_kernels_xrd(KernelTable& t);
 
 }  // namespace smc

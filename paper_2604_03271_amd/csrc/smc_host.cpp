@@ -32,6 +32,7 @@ const KernelTable& kernels() {
         register_kernels_10(g_table);
         register_kernels_11(g_table);
         register_kernels_xps(g_table);
+        register_kernels_xrd(g_table);
     });
     return g_table;
 }
@@ -49,8 +50,10 @@ static bool prior_ok(const smc_prior& p) {
     }
 }
 
-int params_per_peak(int peak_kind) { return peak_kind == SMC_PEAK_GAUSS ? 3 : 4; }
-int params_bg(int bg_kind) { return bg_kind == SMC_BG_NONE ? 0 : (bg_kind == SMC_BG_CONST ? 1 : 2); }
+int params_per_peak(int peak_kind) { return peak_kind == SMC_PEAK_GAUSS ? 3 : (peak_kind == SMC_PEAK_PVOIGT ? 4 : 9); }
+int params_bg(int bg_kind) {
+    return bg_kind == SMC_BG_NONE ? 0 : (bg_kind == SMC_BG_CONST ? 1 : (bg_kind == SMC_BG_XRD ? 4 : 2));
+}
 
 smc_prior component_prior(const smc_problem& p, int K, int j) {
     const int np = params_per_peak(p.peak_kind);
@@ -64,8 +67,17 @@ smc_prior component_prior(const smc_problem& p, int K, int j) {
 smc_status validate(const smc_problem* p, const smc_options* o) {
     if (!p || !o) return SMC_EINVAL;
     if (p->n_points < 1 || !p->x || !p->y) return SMC_EINVAL;
-    if (p->peak_kind != SMC_PEAK_GAUSS && p->peak_kind != SMC_PEAK_PVOIGT) return SMC_EINVAL;
-    if (p->bg_kind < SMC_BG_NONE || p->bg_kind > SMC_BG_SHIRLEY) return SMC_EINVAL;
+    if (p->peak_kind < SMC_PEAK_GAUSS || p->peak_kind > SMC_PEAK_XRD) return SMC_EINVAL;
+    if (p->bg_kind < SMC_BG_NONE || p->bg_kind > SMC_BG_XRD) return SMC_EINVAL;
+    if ((p->peak_kind == SMC_PEAK_XRD) != (p->bg_kind == SMC_BG_XRD)) return SMC_EINVAL;
+    if (p->peak_kind == SMC_PEAK_XRD) {
+        // the XRD powder profile: Poisson counts, reference positions, 0 < 2theta < 180
+        if (p->noise_kind != SMC_NOISE_POISSON || !p->mu_ref || p->n_points > kMaxXrdPoints) return SMC_EINVAL;
+        for (int k = 0; k < p->k_max; ++k)
+            if (!std::isfinite(p->mu_ref[k])) return SMC_EINVAL;
+        for (int i = 0; i < p->n_points; ++i)
+            if (!(p->x[i] > 0.0 && p->x[i] < 180.0)) return SMC_EINVAL;
+    }
     if (p->noise_kind < SMC_NOISE_GAUSS || p->noise_kind > SMC_NOISE_HETERO) return SMC_EINVAL;
     if (p->noise_kind == SMC_NOISE_GAUSS && !(p->sigma > 0.0 && std::isfinite(p->sigma))) return SMC_EINVAL;
     if (xps_model(*p)) {
@@ -166,7 +178,7 @@ Tile choose_tile(const smc_problem& p, int64_t chains, int forced_lanes) {
     // then four wavefronts per chain (a cross-wave LDS reduction per proposal).  Within a
     // class the smallest lane count that still gives 2048 wavefronts, never more lanes than
     // points beyond the smallest configuration.
-    const int max_rows = kPplOf[kNumPpl - 1];
+    const int max_rows = p.peak_kind == SMC_PEAK_XRD ? 20 : kPplOf[kNumPpl - 1];
     const int row_limits[3] = {16, max_rows, max_rows};
     int best = -1;
     for (int cls = 0; cls < 3 && best < 0; ++cls) {
@@ -342,7 +354,7 @@ bool carve_stage_scratch(Arena& a, int P, GroupDesc& g) {
 
 size_t spectrum_bytes(const smc_problem& p, const smc_options& o) {
     const int P = o.n_particles, M = o.waste_free ? P / o.n_moves : P;
-    size_t b = 2 * ((sizeof(float) * p.n_points + 255) & ~static_cast<size_t>(255));
+    size_t b = 2 * ((sizeof(float) * p.n_points + 255) & ~static_cast<size_t>(255)) + 256 + sizeof(float) * p.k_max;
     for (int K = p.k_min; K <= p.k_max; ++K) {
         const int d = K * params_per_peak(p.peak_kind) + params_bg(p.bg_kind);
         b += group_bytes(d, P, M, o.max_stages) + sizeof(GroupDesc) + sizeof(GroupState) + 512;
@@ -375,11 +387,18 @@ bool describe_spectrum(const Spectrum& sp, const smc_options& o, Arena& arena, G
     if (!dx || !dy) return false;
     copies.push_back(PendingCopy{dx, sp.xf.data(), sizeof(float) * p.n_points});
     copies.push_back(PendingCopy{dy, sp.yf.data(), sizeof(float) * p.n_points});
+    float* dmu = nullptr;
+    if (!sp.mref_f.empty()) {
+        dmu = static_cast<float*>(arena.take(sizeof(float) * sp.mref_f.size()));
+        if (!dmu) return false;
+        copies.push_back(PendingCopy{dmu, sp.mref_f.data(), sizeof(float) * sp.mref_f.size()});
+    }
     int si = first_state;
     for (int K = p.k_min; K <= p.k_max; ++K, ++si) {
         GroupDesc g{};
         model_consts(p, K, g);
         g.x = dx;
+        g.mu_ref = dmu;
         g.y = dy;
         g.P = P;
         g.M = M;
@@ -429,6 +448,13 @@ void Spectrum::assign(const smc_problem& p) {
         prob.peak_prior_k = ppk.data();
     } else {
         ppk.clear();
+    }
+    mref.clear();
+    mref_f.clear();
+    if (p.mu_ref) {
+        mref.assign(p.mu_ref, p.mu_ref + p.k_max);
+        for (double v : mref) mref_f.push_back(static_cast<float>(v));
+        prob.mu_ref = mref.data();
     }
 }
 
@@ -798,6 +824,7 @@ extern "C" smc_status smc_posterior_summary(smc_ctx* c, int32_t K, const double*
     const int gi = K - c->kmin;
     if (c->states[gi].beta < 1.0) return SMC_ESTATE;
     const GroupDesc& g = c->groups[gi];
+    if (relabel && g.peak_kind == SMC_PEAK_XRD) return SMC_EINVAL;   // XRD peaks carry their own mu_ref
     const int n_peaks = relabel ? K : 0;
     return posterior_summary(g.theta, g.d, g.P, n_peaks, g.np, probs, n_probs, mean, quant, c->stream);
 }

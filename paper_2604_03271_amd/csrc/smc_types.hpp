@@ -80,6 +80,7 @@ struct GroupDesc {
     StageNewton* nst;           // [2] temperature-search state
     unsigned long long* ctot;   // [nchunk] integer weight totals, then their exclusive prefix
     int32_t nchunk, pad3;
+    const float* mu_ref;        // XRD peaks: reference positions [K]
 };
 
 // One workgroup of the move / energy kernels: chains [chain0, chain0 + nchains) of a group.

@@ -16,8 +16,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsmc.so")
 
-PEAK = {"gauss": 0, "pvoigt": 1}
-BG = {"none": 0, "const": 1, "linear": 2, "shirley": 3}
+PEAK = {"gauss": 0, "pvoigt": 1, "xrd": 2}
+BG = {"none": 0, "const": 1, "linear": 2, "shirley": 3, "xrd": 4}
 NOISE = {"gauss": 0, "poisson": 1, "hetero": 2}
 PRIOR = {"uniform": 0, "gamma": 1, "normal": 2, "fixed": 3}
 
@@ -50,6 +50,7 @@ class smc_problem(ctypes.Structure):
         ("k_max", ctypes.c_int32),
         ("uid", ctypes.c_uint32),
         ("noise_s", ctypes.c_double * 3),
+        ("mu_ref", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -194,6 +195,12 @@ class Problem:
         ns = getattr(spec, "noise_s", None) or (0.0, 0.0, 0.0)
         for q in range(3):
             p.noise_s[q] = float(ns[q])
+        mr = getattr(spec, "mu_ref", None)
+        self._mu_ref = None if mr is None else np.ascontiguousarray(mr, dtype=np.float64)
+        if self._mu_ref is not None:
+            if self._mu_ref.size < p.k_max:
+                raise ValueError("mu_ref needs one reference position per candidate peak (k_max)")
+            p.mu_ref = _pd(self._mu_ref)
         self.c = p
 
     @property

@@ -360,21 +360,22 @@ def xrd_priors(y, K):
     peak = [("gamma", 4.0, 4.0 / (ymax - ymin)), ("normal", 0.0, 0.05), ("uniform", 0.0, 1.0), ("gamma", 5.0, 4.0),
             ("gamma", 1.0, 10.0), ("gamma", 1.0, 10.0), ("gamma", 2.0, 20.0), ("gamma", 2.0, 20.0),
             ("gamma", 1.0, 10.0)]
-    bg = [("gamma", 2.0, 1.0 / ymax), ("gamma", 2.0, 0.4), ("uniform", 0.0, 1.0),
-          ("uniform", ymin - float(np.sqrt(ymin)), ymin + float(np.sqrt(ymin)))]
+    h = float(np.sqrt(max(ymin, 1.0)))   # at least one count either side when the pattern has zeros
+    bg = [("gamma", 2.0, 1.0 / ymax), ("gamma", 2.0, 0.4), ("uniform", 0.0, 1.0), ("uniform", ymin - h, ymin + h)]
     return peak, bg
 
 
-def xrd_powder(n: int = 1000, index: int = 0) -> Spectrum:
+def xrd_powder(n: int = 1000, index: int = 0, lo: float = 10.0, hi: float = 60.0, scale: float = 1.0) -> Spectrum:
     """The paper's artificial XRD pattern (three TiO2 phases, pseudo-Voigt background), N points on
-    2theta in [10, 60], Poisson counts; the free energy at K = 3."""
+    2theta in [lo, hi] (the paper's 10-60 by default), Poisson counts of scale times the
+    intensities; the free energy at K = 3."""
     rng = np.random.default_rng(1000 * 8 + index)
-    x = f32(10.0 + 50.0 * np.arange(n) / (n - 1))
+    x = f32(lo + (hi - lo) * np.arange(n) / (n - 1))
     f = np.full(n, XRD_BG_TRUE[3]) + XRD_BG_TRUE[0] * _gen_xrd_pv(x, 0.0, XRD_BG_TRUE[1], XRD_BG_TRUE[1], XRD_BG_TRUE[2])
     names = ["rutile", "anatase", "brookite"]
     for nm in names:
         f = f + _gen_xrd_peak(x, XRD_MU_REF[nm], XRD_TRUE[nm])
-    y = rng.poisson(f).astype(np.float64)
+    y = rng.poisson(scale * f).astype(np.float64)
     pp, bgp = xrd_priors(y, 3)
     sp = Spectrum(x, y, "xrd", "xrd", "poisson", 0.0, pp, bgp, 3, 3,
                   truth={"K": 3, "peaks": [XRD_TRUE[nm] for nm in names], "bg": XRD_BG_TRUE}, uid=8000 + index)

@@ -145,3 +145,43 @@ def test_xps_model_needs_increasing_x_and_at_most_1024_points():
     assert _init_status(sp) == native.SMC_EINVAL
     big = W.xps_shirley(index=1, n=1100, k_min=2, k_max=2)
     assert _init_status(big) == native.SMC_EINVAL
+
+
+def _xrd(**kw):
+    sp = W.xrd_powder(n=400, index=0)
+    sp.x = sp.x.copy()
+    sp.y = sp.y.copy()
+    sp.mu_ref = list(sp.mu_ref)
+    for k, v in kw.items():
+        setattr(sp, k, v)
+    return sp
+
+
+def test_xrd_dim():
+    assert native.Problem(_xrd()).dim(3) == 3 * 9 + 4
+
+
+@pytest.mark.parametrize("change", [
+    dict(noise_kind="gauss", sigma=1.0),     # the XRD profile takes Poisson counts
+    dict(bg_kind="linear"),                  # XRD peaks need the XRD background
+    dict(peak_kind="pvoigt", peak_prior=[("uniform", 0, 1)] * 4),   # XRD background needs XRD peaks
+    dict(mu_ref=None),                       # reference positions are required
+    dict(mu_ref=[27.4, float("nan"), 30.8]),
+])
+def test_xrd_model_combinations_rejected(change):
+    assert _init_status(_xrd(**change)) == native.SMC_EINVAL
+
+
+@pytest.mark.parametrize("i,v", [(0, 0.0), (5, -3.0), (399, 180.0), (399, 200.0)])
+def test_xrd_two_theta_must_lie_in_open_range(i, v):
+    sp = _xrd()
+    sp.x[i] = v
+    assert _init_status(sp) == native.SMC_EINVAL
+
+
+def test_xrd_point_limit_and_short_mu_ref():
+    assert _init_status(_xrd()) != native.SMC_EINVAL            # valid: reaches the device check
+    assert _init_status(W.xrd_powder(n=5120)) != native.SMC_EINVAL
+    assert _init_status(W.xrd_powder(n=5121)) == native.SMC_EINVAL
+    with pytest.raises(ValueError):
+        native.Problem(_xrd(mu_ref=[27.4, 25.3]))
