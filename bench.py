@@ -216,7 +216,7 @@ def _workload(name, native_options, workloads, particles):
     elif name.startswith("xrd-"):
         N = int(name.split("-")[1])
         spec = workloads.xrd_powder(n=N, index=0)
-        P, n = particles or 262144, 10
+        P, n = particles or 250_000, 10
         desc = (f"paper XRD artificial pattern N={N} (2theta 10-60, three TiO2 phases, Poisson counts), "
                 f"free energy at K=3 (31 parameters), P={P}, waste-free n={n}")
     else:

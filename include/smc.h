@@ -109,7 +109,8 @@ typedef struct {
     int32_t k_min, k_max;        /* candidate peak counts, 1 <= k_min <= k_max */
     uint32_t uid;                /* identity of the spectrum; part of the random-number key */
     double noise_s[3];           /* s0, s1, s2 >= 0 of the heteroscedastic noise (ignored otherwise) */
-    const double* mu_ref;        /* (host) XRD peaks: reference positions [k_max]; NULL otherwise */
+    const double* mu_ref;        /* (host) XRD peaks: reference positions [k_max], copied at init and
+                                    rounded to FP32; NULL otherwise */
 } smc_problem;
 
 typedef struct {

@@ -379,5 +379,5 @@ def xrd_powder(n: int = 1000, index: int = 0, lo: float = 10.0, hi: float = 60.0
     pp, bgp = xrd_priors(y, 3)
     sp = Spectrum(x, y, "xrd", "xrd", "poisson", 0.0, pp, bgp, 3, 3,
                   truth={"K": 3, "peaks": [XRD_TRUE[nm] for nm in names], "bg": XRD_BG_TRUE}, uid=8000 + index)
-    sp.mu_ref = [XRD_MU_REF[nm] for nm in names]
+    sp.mu_ref = [float(f32(XRD_MU_REF[nm])) for nm in names]   # FP32-exact, as x
     return sp

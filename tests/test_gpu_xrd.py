@@ -20,7 +20,7 @@ EXTRA_REF = [36.08, 48.05, 53.89, 55.06, 41.23]   # further reference positions 
 def _spec(n, K, index=0, **kw):
     sp = W.xrd_powder(n=n, index=index, **kw)
     sp.k_min = sp.k_max = K
-    sp.mu_ref = (list(sp.mu_ref) + EXTRA_REF)[:K]
+    sp.mu_ref = [float(np.float32(m)) for m in (list(sp.mu_ref) + EXTRA_REF)[:K]]   # FP32-exact, as x
     return sp
 
 
@@ -44,7 +44,7 @@ def _thetas(rng, spec, K, m, n_undefined=0):
     return f32(np.array(rows))
 
 
-@pytest.mark.parametrize("n,K,lanes", [(1000, 3, 0), (5120, 3, 0), (2000, 2, 64), (300, 1, 16), (600, 5, 32),
+@pytest.mark.parametrize("n,K,lanes", [(1000, 3, 0), (5120, 3, 0), (1200, 2, 64), (300, 1, 16), (600, 5, 32),
                                        (4000, 4, 256)])
 def test_energies_match_reference(orc, n, K, lanes):
     torch = torch_cuda()
@@ -62,7 +62,7 @@ def test_energies_match_reference(orc, n, K, lanes):
     assert np.array_equal(finite, np.isfinite(got))
     assert np.all(got[~finite] > 0)
     rel = np.abs(got[finite] - ref[finite]) / np.abs(ref[finite])
-    assert rel.max() <= 2e-5, (rel.max(), int(np.argmax(rel)))
+    assert rel.max() <= 1e-5, (rel.max(), int(np.argmax(rel)))
 
 
 def test_init_draws_follow_reference_streams(orc):
@@ -159,4 +159,5 @@ def test_log_evidence_parity_with_reference(orc):
         o.append([orc.run(opr, K, P, 8, False, seed + 1000, spec.uid).log_evidence for K in (1, 2)])
     d, se = _stat_parity(g, o)
     say("xrd diff", d, "se", se, "gpu", np.mean(g, 0), "ref", np.mean(o, 0))
-    assert np.all(np.abs(d) <= 3 * se + 1e-9) and np.all(np.abs(d) <= 0.2 + 3 * se), (d, se)
+    assert np.all(np.abs(d) <= 3 * se + 1e-9) and np.all(np.abs(d) <= 0.05 + 3 * se), (d, se)
+    assert np.argmax(np.mean(g, 0)) == np.argmax(np.mean(o, 0))
