@@ -18,7 +18,7 @@ the prior's support) covers N points.
 spectra instead (App. B: N = 300 / 1000 / 3000, n = 10 / 10 / 100 moves per
 temperature, free energy at the true K only), by default at the largest
 particle counts the paper runs (10^6, and 3 x 10^6 for K = 30).
---workload xrd-1000 | xrd-5000 times the paper's artificial XRD pattern (App. E:
+--workload xrd-1000 | xrd-5000 | xrd-10000 times the paper's artificial XRD pattern (App. E:
 three TiO2 phases at reference positions, pseudo-Voigt background, Poisson
 counts, N points on 2theta 10-60 degrees), free energy at K = 3, n = 10.
 
@@ -236,7 +236,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="xps-pv",
                     choices=["xps-pv", "paper-k3", "paper-k10", "paper-k30", "xps-shirley", "xrd-1000",
-                             "xrd-5000"])
+                             "xrd-5000", "xrd-10000"])
     ap.add_argument("--particles", type=int, default=0, help="particles per K (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")

@@ -245,8 +245,8 @@ struct PoolView {
         for (size_t bi = 0; bi < buckets.size(); ++bi) {
             const Bucket& b = buckets[bi];
             const void* efn = kernels().energy[b.pk][b.nz][b.tile.lc][b.tile.pi];
-            if (launch_tiled(efn, energy_ranges[bi].second, b.lds_energy, d_groups, d_scratch + energy_ranges[bi].first,
-                             s) != hipSuccess)
+            if (launch_tiled(efn, b.tile, energy_ranges[bi].second, b.lds_energy, d_groups,
+                             d_scratch + energy_ranges[bi].first, s) != hipSuccess)
                 return SMC_EDEVICE;
         }
         // the scratch list must stay valid until the launches have read it
@@ -266,7 +266,7 @@ struct PoolView {
         if (e != hipSuccess) return e;
         for (const Bucket& b : buckets) {
             const void* mfn = kernels().move[b.pk][b.nz][b.tile.lc][b.tile.pi];
-            e = launch_tiled(mfn, b.work_cnt, b.lds_move, d_groups, d_work + b.work_off, s);
+            e = launch_tiled(mfn, b.tile, b.work_cnt, b.lds_move, d_groups, d_work + b.work_off, s);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;

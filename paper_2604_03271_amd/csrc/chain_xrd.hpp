@@ -58,6 +58,7 @@ __device__ __forceinline__ bool xrd_linear(bool is_bg, int q) { return is_bg ? q
 template <int L, int WPC, int PPL>
 struct XrdChain {
     static constexpr int LC = L * WPC;
+    static constexpr int TPB = LC > 256 ? LC : 256;   // threads per workgroup
     float x[PPL], tn[PPL], y[PPL];
     float D[PPL];
     float S1[PPL], S2[PPL];
@@ -209,18 +210,21 @@ struct XrdChain {
     }
 };
 
+// Workgroups of TPB threads hold TPB / LC chains; XCD dealing in chunks of 16 chains,
+// whole 64-byte lines of the component-major parameter arrays.
 template <int L, int WPC, int PPL>
-__global__ void __launch_bounds__(256) k_energy_xrd(const GroupDesc* __restrict__ groups,
-                                                    const MoveWork* __restrict__ work) {
+__global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256) k_energy_xrd(const GroupDesc* __restrict__ groups,
+                                                                             const MoveWork* __restrict__ work) {
     using CS = XrdChain<L, WPC, PPL>;
     constexpr int LC = CS::LC;
-    const MoveWork w = work[xcd_block(blockIdx.x, gridDim.x, LC / 16)];
+    constexpr int CPW = CS::TPB / LC;
+    const MoveWork w = work[xcd_block(blockIdx.x, gridDim.x, 16 / CPW)];
     const GroupDesc& g = groups[w.group];
     extern __shared__ float lds[];
     const int slot = threadIdx.x / LC, lane = threadIdx.x % LC;
     const int d = g.d;
     float* th = lds + slot * d;
-    float* red = lds + (256 / LC) * d;
+    float* red = lds + CPW * d;
     const bool active = slot < w.nchains;
     const int i = w.chain0 + slot;
     if (active)
@@ -237,12 +241,13 @@ __global__ void __launch_bounds__(256) k_energy_xrd(const GroupDesc* __restrict_
 constexpr int xrd_min_waves(int points) { return points <= 6 ? 4 : (points <= 10 ? 3 : 2); }
 
 template <int L, int WPC, int PPL>
-__global__ void __launch_bounds__(256, xrd_min_waves(PPL)) k_move_xrd(const GroupDesc* __restrict__ groups,
-                                                                       const MoveWork* __restrict__ work) {
+__global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256, xrd_min_waves(PPL))
+    k_move_xrd(const GroupDesc* __restrict__ groups, const MoveWork* __restrict__ work) {
     using CS = XrdChain<L, WPC, PPL>;
     constexpr int LC = CS::LC;
-    constexpr int CPW = 256 / LC;
-    const MoveWork w = work[xcd_block(blockIdx.x, gridDim.x, LC / 16)];
+    constexpr int TPB = CS::TPB;
+    constexpr int CPW = TPB / LC;
+    const MoveWork w = work[xcd_block(blockIdx.x, gridDim.x, 16 / CPW)];
     const GroupDesc& g = groups[w.group];
     GroupState* st = g.st;
     if (st->done) return;
@@ -266,7 +271,7 @@ __global__ void __launch_bounds__(256, xrd_min_waves(PPL)) k_move_xrd(const Grou
     const uint32_t stage = static_cast<uint32_t>(st->stage);
     const uint32_t K = static_cast<uint32_t>(g.K);
 
-    for (int j = threadIdx.x; j < d; j += 256) {
+    for (int j = threadIdx.x; j < d; j += TPB) {
         accc[j] = 0u;
         pri[j] = g.prior[j];
     }
@@ -334,7 +339,7 @@ __global__ void __launch_bounds__(256, xrd_min_waves(PPL)) k_move_xrd(const Grou
         if (my_linear) atomicAdd(&nevals[1], my_linear);
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < d; j += 256)
+    for (int j = threadIdx.x; j < d; j += TPB)
         if (accc[j]) atomicAdd(&g.acc[j], accc[j]);
     if (threadIdx.x == 0 && (nevals[0] | nevals[1])) {
         atomicAdd(&g.st->evals, static_cast<unsigned long long>(nevals[0]) + nevals[1]);

@@ -13,12 +13,17 @@ namespace smc {
 
 constexpr int kMaxK = 64;
 constexpr int kMaxXpsPoints = 1024;   // XPS model form: 64 lanes x 16 points
-constexpr int kMaxXrdPoints = 5120;   // XRD powder profile: 256 lanes x 20 points
+constexpr int kMaxXrdPoints = 10240;  // XRD powder profile: 512 lanes x 20 points
 
 struct Tile {
     int lc, pi, lanes, ppl;
     bool valid;
 };
+
+// Threads per workgroup of the move / energy kernels: 256 (several chains of up to 256
+// lanes), or one chain of more lanes.
+inline int tile_threads(const Tile& t) { return t.lanes > 256 ? t.lanes : 256; }
+inline int tile_chains_per_wg(const Tile& t) { return tile_threads(t) / t.lanes; }
 
 struct Arena {
     void* base;
@@ -65,8 +70,8 @@ size_t move_lds_bytes(const Tile& t, int d);
 size_t energy_lds_bytes(const Tile& t, int d);
 void build_work(const std::vector<int>& groups, const std::vector<int>& chains_of, const Tile& t,
                 std::vector<MoveWork>& out);
-hipError_t launch_tiled(const void* fn, int n_work, size_t lds, const GroupDesc* groups, const MoveWork* work,
-                        hipStream_t s);
+hipError_t launch_tiled(const void* fn, const Tile& t, int n_work, size_t lds, const GroupDesc* groups,
+                        const MoveWork* work, hipStream_t s);
 size_t group_bytes(int d, int P, int M, int max_stages);
 size_t spectrum_bytes(const smc_problem& p, const smc_options& o);
 bool describe_spectrum(const Spectrum& sp, const smc_options& o, Arena& arena, GroupState* d_states_base,

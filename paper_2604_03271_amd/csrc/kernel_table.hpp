@@ -1,7 +1,7 @@
 // kernel_table.hpp -- host-side table of the move / energy kernel instantiations.
 //
-// Tiles: lanes per chain (16, 32 or 64 lanes of one wavefront, or 4 whole
-// wavefronts = 256 lanes) x points per lane (PPL, compile time; the smallest
+// Tiles: lanes per chain (16, 32 or 64 lanes of one wavefront, or 4 or 8 whole
+// wavefronts = 256 or 512 lanes) x points per lane (PPL, compile time; the smallest
 // listed value >= ceil(N / lanes), points beyond N padded with zero-weight ones).
 #pragma once
 
@@ -9,15 +9,16 @@
 
 namespace smc {
 
-constexpr int kNumLaneCfg = 4;            // 16x1, 32x1, 64x1, 64x4
-constexpr int kLanesOf[kNumLaneCfg] = {16, 32, 64, 256};
+constexpr int kNumLaneCfg = 5;            // 16x1, 32x1, 64x1, 64x4, 64x8
+constexpr int kLanesOf[kNumLaneCfg] = {16, 32, 64, 256, 512};
 constexpr int kNumPpl = 16;
 constexpr int kPplOf[kNumPpl] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32};
 
 // [peak kind][noise kind][lane configuration][points per lane]; noise kind 2 (heteroscedastic,
 // with the Shirley background) exists for pseudo-Voigt peaks, one-wavefront lane
 // configurations and at most 16 points per lane only; peak kind 2 (XRD) for Poisson counts
-// and at most 20 points per lane (other entries are null).
+// and at most 20 points per lane; 512 lanes (workgroups of 512 threads, one chain) for XRD
+// only (other entries are null).
 struct KernelTable {
     const void* move[3][3][kNumLaneCfg][kNumPpl];
     const void* energy[3][3][kNumLaneCfg][kNumPpl];

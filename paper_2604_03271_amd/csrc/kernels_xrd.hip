@@ -1,5 +1,5 @@
 // Move / energy kernel instantiations of the XRD powder profile with Poisson counts: every lane
-// configuration, at most 20 points per lane.
+// configuration (512-lane chains included), at most 20 points per lane.
 #include "chain_xrd.hpp"
 #include "kernel_table.hpp"
 
@@ -25,6 +25,7 @@ void register_kernels_xrd(KernelTable& t) {
     reg_xrd_list<32, 1, 1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20>(t, 1);
     reg_xrd_list<64, 1, 1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20>(t, 2);
     reg_xrd_list<64, 4, 1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20>(t, 3);
+    reg_xrd_list<64, 8, 1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20>(t, 4);
 }
 
 }  // namespace smc

@@ -116,8 +116,9 @@ smc_status validate(const smc_problem* p, const smc_options* o) {
     if (!(o->ess_frac > 0.0 && o->ess_frac < 1.0)) return SMC_EINVAL;
     if (o->bisect_iters < 1 || o->bisect_iters > 200 || o->max_stages < 1) return SMC_EINVAL;
     if (o->lanes_per_chain != 0 && o->lanes_per_chain != 16 && o->lanes_per_chain != 32 &&
-        o->lanes_per_chain != 64 && o->lanes_per_chain != 256)
+        o->lanes_per_chain != 64 && o->lanes_per_chain != 256 && o->lanes_per_chain != 512)
         return SMC_EINVAL;
+    if (o->lanes_per_chain == 512 && p->peak_kind != SMC_PEAK_XRD) return SMC_EINVAL;
     return SMC_OK;
 }
 
@@ -175,9 +176,10 @@ Tile choose_tile(const smc_problem& p, int64_t chains, int forced_lanes) {
     }
     // Preference: chains inside one wavefront with at most 16 points per lane (the move
     // kernel keeps 4+ waves per SIMD there), then up to 32 points per lane (2-3 waves),
-    // then four wavefronts per chain (a cross-wave LDS reduction per proposal).  Within a
-    // class the smallest lane count that still gives 2048 wavefronts, never more lanes than
-    // points beyond the smallest configuration.
+    // then four or eight wavefronts per chain (a cross-wave LDS reduction per proposal).
+    // Within a class the smallest lane count that still gives 2048 wavefronts, never more
+    // lanes than points beyond the smallest configuration; only configurations the model
+    // family has kernels for.
     const int max_rows = p.peak_kind == SMC_PEAK_XRD ? 20 : kPplOf[kNumPpl - 1];
     const int row_limits[3] = {16, max_rows, max_rows};
     int best = -1;
@@ -185,6 +187,7 @@ Tile choose_tile(const smc_problem& p, int64_t chains, int forced_lanes) {
         for (int lc = 0; lc < kNumLaneCfg; ++lc) {
             const int lanes = kLanesOf[lc];
             if (forced_lanes ? lanes != forced_lanes : ((cls < 2) != (lanes <= 64))) continue;
+            if (!kernels().move[p.peak_kind][p.noise_kind][lc][0]) continue;
             const int rows = (n_points + lanes - 1) / lanes;
             if (rows > (forced_lanes ? max_rows : row_limits[cls])) continue;
             if (!forced_lanes && best >= 0 && kLanesOf[best] >= n_points) break;
@@ -210,32 +213,37 @@ bool tile_has_kernels(const smc_problem& p, const Tile& t) {
            kernels().energy[p.peak_kind][p.noise_kind][t.lc][t.pi];
 }
 
+// Cross-wave reduction slots (two per wavefront of a chain, double-buffered) and the
+// two evaluation counters.
+static size_t reduce_floats(const Tile& t) { return 2 * static_cast<size_t>(t.lanes > 64 ? t.lanes / 64 : 1) + 2; }
+
 size_t move_lds_bytes(const Tile& t, int d) {
-    const int cpw = 256 / t.lanes;
-    return sizeof(DevPrior) * d + sizeof(float) * (static_cast<size_t>(cpw) * 3 * d + d + 12);
+    const int cpw = tile_chains_per_wg(t);
+    return sizeof(DevPrior) * d + sizeof(float) * (static_cast<size_t>(cpw) * 3 * d + d + reduce_floats(t));
 }
 
 size_t energy_lds_bytes(const Tile& t, int d) {
-    const int cpw = 256 / t.lanes;
-    return sizeof(float) * (static_cast<size_t>(cpw) * d + 8);
+    const int cpw = tile_chains_per_wg(t);
+    return sizeof(float) * (static_cast<size_t>(cpw) * d + reduce_floats(t));
 }
 
 // Work items: groups in the given order, each split into workgroups of
-// 256 / lanes chains.
+// tile_chains_per_wg chains.
 void build_work(const std::vector<int>& groups, const std::vector<int>& chains_of, const Tile& t,
                 std::vector<MoveWork>& out) {
-    const int cpw = 256 / t.lanes;
+    const int cpw = tile_chains_per_wg(t);
     for (int g : groups) {
         const int nc = chains_of[g];
         for (int c0 = 0; c0 < nc; c0 += cpw) out.push_back(MoveWork{g, c0, std::min(cpw, nc - c0), 0});
     }
 }
 
-hipError_t launch_tiled(const void* fn, int n_work, size_t lds, const GroupDesc* groups, const MoveWork* work,
-                        hipStream_t s) {
+hipError_t launch_tiled(const void* fn, const Tile& t, int n_work, size_t lds, const GroupDesc* groups,
+                        const MoveWork* work, hipStream_t s) {
     if (n_work <= 0) return hipSuccess;
     void* args[] = {&groups, &work};
-    return hipLaunchKernel(fn, dim3(static_cast<unsigned>(n_work)), dim3(256), args, lds, s);
+    return hipLaunchKernel(fn, dim3(static_cast<unsigned>(n_work)), dim3(static_cast<unsigned>(tile_threads(t))), args,
+                           lds, s);
 }
 
 // ------------------------------------------------------------------ device arena
@@ -501,7 +509,7 @@ static smc_status stage0(smc_ctx* c) {
         if (launch_draw(c->d_groups, gi, static_cast<int64_t>(c->groups[gi].d) * P, c->stream) != hipSuccess)
             return SMC_EDEVICE;
     const void* efn = kernels().energy[c->spec.prob.peak_kind][c->spec.prob.noise_kind][c->tile.lc][c->tile.pi];
-    if (launch_tiled(efn, c->n_init_work, c->lds_energy, c->d_groups, c->d_init_work, c->stream) != hipSuccess)
+    if (launch_tiled(efn, c->tile, c->n_init_work, c->lds_energy, c->d_groups, c->d_init_work, c->stream) != hipSuccess)
         return SMC_EDEVICE;
     c->stage0_evals = static_cast<uint64_t>(P) * c->ng;
     return SMC_OK;
@@ -675,7 +683,7 @@ static hipError_t timed_stage(smc_ctx* c, const GroupDesc* groups, int n) {
 static hipError_t timed_move(smc_ctx* c, const void* fn, int n_work, const MoveWork* work) {
     const bool prof = c->opt.profile && !c->ev_move;
     if (prof && hipEventRecord(c->ev[0], c->stream) != hipSuccess) return hipErrorUnknown;
-    hipError_t e = launch_tiled(fn, n_work, c->lds_move, c->d_groups, work, c->stream);
+    hipError_t e = launch_tiled(fn, c->tile, n_work, c->lds_move, c->d_groups, work, c->stream);
     if (prof && e == hipSuccess) {
         e = hipEventRecord(c->ev[1], c->stream);
         c->ev_move = true;

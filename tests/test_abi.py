@@ -76,6 +76,7 @@ def _init_status(spec, **kw):
     (lambda s: None, {"ess_frac": 1.0}),
     (lambda s: None, {"bisect_iters": 0}),
     (lambda s: None, {"lanes_per_chain": 48}),
+    (lambda s: None, {"lanes_per_chain": 512}),   # 512-lane chains exist for the XRD profile only
     (lambda s: None, {"n_particles": 200_000_000}),   # 12 components x P beyond 32-bit offsets
 ])
 def test_invalid_problems_rejected_on_host(mutate, kw):
@@ -181,7 +182,7 @@ def test_xrd_two_theta_must_lie_in_open_range(i, v):
 
 def test_xrd_point_limit_and_short_mu_ref():
     assert _init_status(_xrd()) != native.SMC_EINVAL            # valid: reaches the device check
-    assert _init_status(W.xrd_powder(n=5120)) != native.SMC_EINVAL
-    assert _init_status(W.xrd_powder(n=5121)) == native.SMC_EINVAL
+    assert _init_status(W.xrd_powder(n=10240)) != native.SMC_EINVAL
+    assert _init_status(W.xrd_powder(n=10241)) == native.SMC_EINVAL
     with pytest.raises(ValueError):
         native.Problem(_xrd(mu_ref=[27.4, 25.3]))

@@ -45,7 +45,7 @@ def _thetas(rng, spec, K, m, n_undefined=0):
 
 
 @pytest.mark.parametrize("n,K,lanes", [(1000, 3, 0), (5120, 3, 0), (1200, 2, 64), (300, 1, 16), (600, 5, 32),
-                                       (4000, 4, 256)])
+                                       (4000, 4, 256), (10000, 3, 0), (10240, 2, 512), (3001, 3, 512)])
 def test_energies_match_reference(orc, n, K, lanes):
     torch = torch_cuda()
     spec = _spec(n, K, index=1)
@@ -88,7 +88,7 @@ def test_init_draws_follow_reference_streams(orc):
 
 
 @pytest.mark.parametrize("n,K,M,nm,wf,beta", [(1000, 3, 128, 4, True, 1e-4), (400, 2, 64, 2, False, 1e-3),
-                                              (5120, 1, 96, 2, True, 1e-2)])
+                                              (5120, 1, 96, 2, True, 1e-2), (10000, 3, 40, 2, True, 1e-4)])
 def test_move_matches_reference(orc, n, K, M, nm, wf, beta):
     torch = torch_cuda()
     spec = _spec(n, K, index=4)
