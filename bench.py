@@ -201,7 +201,7 @@ def served(native, workloads, n_arrivals, rate, budget=64 << 30):
             "offered_per_s": rate}
 
 
-def _workload(name, native_options, workloads, particles):
+def _workload(name, native_options, workloads, particles, lanes=0):
     """(spectrum, options, description) of a named workload."""
     if name == "xps-pv":
         spec = workloads.config2(0)
@@ -226,7 +226,7 @@ def _workload(name, native_options, workloads, particles):
         P = particles or (3_000_000 if K == 30 else 1_000_000)
         desc = (f"paper Gaussian-peak spectrum K={K}, N={spec.n}, sigma={spec.sigma}, free energy at K={K}, "
                 f"P={P}, waste-free n={n}")
-    return spec, native_options(n_particles=P, n_moves=n, waste_free=True, seed=0, profile=True), desc
+    return spec, native_options(n_particles=P, n_moves=n, waste_free=True, seed=0, profile=True, lanes_per_chain=lanes), desc
 
 
 def main():
@@ -238,6 +238,7 @@ def main():
                     choices=["xps-pv", "paper-k3", "paper-k10", "paper-k30", "xps-shirley", "xrd-1000",
                              "xrd-5000", "xrd-10000"])
     ap.add_argument("--particles", type=int, default=0, help="particles per K (default: the workload's)")
+    ap.add_argument("--lanes", type=int, default=0, help="lanes per chain (default: the library's tile rule)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--batch", type=int, default=0, help="also run the config-4 batch with this many spectra")
@@ -263,7 +264,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    spec, opt, desc = _workload(args.workload, native.options, workloads, args.particles)
+    spec, opt, desc = _workload(args.workload, native.options, workloads, args.particles, args.lanes)
     P, n = opt.n_particles, opt.n_moves
     ks = range(spec.k_min, spec.k_max + 1)
     s = native.Sampler(spec, opt)
@@ -336,7 +337,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc,
                    "n_points": spec.n, "k_range": [spec.k_min, spec.k_max], "particles_per_k": P, "n_moves": n,
-                   "parallelism": "single GPU, all K in one launch"},
+                   "parallelism": "single GPU, all K in one launch", "lanes_per_chain": args.lanes or "auto"},
         "spectra_per_s": args.steps / elapsed,
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "stages_max": int(np.max(stages)),

@@ -132,7 +132,7 @@ __device__ __forceinline__ PeakC peak_consts(const float* th) {
         const float s = th[2];
         q.mu = th[1];
         q.s2 = s * s;
-        q.c = -1.0f / q.s2;
+        q.c = -__builtin_amdgcn_rcpf(q.s2);   // v_rcp (1 ulp): no IEEE division sequence per proposal
         q.aG = th[0] * th[3];
         q.aL = th[0] * (1.0f - th[3]) * q.s2;
     }
