@@ -100,6 +100,9 @@ CASES = [
     ("pvoigt", "const", "poisson", 999, 4, 64),
     ("gauss", "const", "poisson", 300, 3, 32),
     ("pvoigt", "linear", "poisson", 129, 2, 16),
+    ("gauss", "none", "gauss", 1, 1, 0),           # a single point
+    ("pvoigt", "linear", "gauss", 8192, 4, 0),     # the largest N of these families (256 lanes x 32)
+    ("gauss", "const", "gauss", 2000, 64, 0),      # the largest K
 ]
 
 
