@@ -351,12 +351,6 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL)) k_move(const
                 const int j0 = is_bg ? g.K * g.np : k * g.np;
                 const int nq = is_bg ? g.nbg : g.np;
                 if (k > 0) cs.transition(g, th, k - 1, k);
-                // Gaussian peaks: constants of the current term, updated on every accept, and a
-                // proposal changes one of them.  Pseudo-Voigt peaks rebuild all five from the
-                // parameters without branches (measured faster there: the per-component cases
-                // need more of them).
-                PeakC qc{};
-                if constexpr (PK == SMC_PEAK_GAUSS) qc = CS::term_consts(g, th, k);
                 for (int q = 0; q < nq; ++q) {
                     const int j = j0 + q;
                     const DevPrior pr = pri[j];
@@ -365,24 +359,14 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL)) k_move(const
                     const float vn = vo + inc[j];
                     if (!prior_in_support(pr, vn)) continue;
                     // constants of the term with component j replaced
-                    PeakC qn = qc;
-                    if constexpr (PK == SMC_PEAK_GAUSS) {
-                        if (is_bg) {
-                            if (q == 0) qn.aG = vn;
-                            else qn.aL = vn;
-                        } else {
-                            qn = gauss_consts_with(qc, q, vn);
-                        }
-                    } else {
-                        float tmp[4];
-                        const float* base = th + j0;
+                    float tmp[4];
+                    const float* base = th + j0;
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) tmp[u] = (u < nq) ? base[u] : 0.0f;
+                    for (int u = 0; u < 4; ++u) tmp[u] = (u < nq) ? base[u] : 0.0f;
 #pragma unroll
-                        for (int u = 0; u < 4; ++u)
-                            if (u == q) tmp[u] = vn;
-                        qn = is_bg ? bg_consts(tmp, g.nbg) : peak_consts<PK>(tmp);
-                    }
+                    for (int u = 0; u < 4; ++u)
+                        if (u == q) tmp[u] = vn;
+                    const PeakC qn = is_bg ? bg_consts(tmp, g.nbg) : peak_consts<PK>(tmp);
                     const bool linear = is_bg || linear_component<PK>(q);
                     float part;
                     if (is_bg) {
@@ -399,7 +383,6 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL)) k_move(const
                     const float log_alpha = -beta * (En - E) + prior_log_ratio(pr, vn, vo);
                     if (lnu[j] < log_alpha) {
                         E = En;
-                        if constexpr (PK == SMC_PEAK_GAUSS) qc = qn;
                         if (!linear) cs.accept_shape(qn);
                         th[j] = vn;
                         if (lane == 0) atomicAdd(&accc[j], 1u);

@@ -139,17 +139,6 @@ __device__ __forceinline__ PeakC peak_consts(const float* th) {
     return q;
 }
 
-// Constants of a Gaussian peak whose component q is replaced by vn, from the constants qc
-// of the peak as it stands; the same expressions as peak_consts, so the results are
-// bit-identical, at one VALU operation per proposal.
-__device__ __forceinline__ PeakC gauss_consts_with(const PeakC& qc, int q, float vn) {
-    PeakC qn = qc;
-    if (q == 0) qn.aG = vn;
-    else if (q == 1) qn.mu = vn;
-    else qn.c = -0.5f * kLog2e * vn;
-    return qn;
-}
-
 __device__ __forceinline__ PeakC bg_consts(const float* th, int nbg) {
     PeakC q{};
     q.aG = nbg > 0 ? th[0] : 0.0f;
