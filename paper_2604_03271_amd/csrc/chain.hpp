@@ -272,18 +272,24 @@ __global__ void __launch_bounds__(256) k_energy(const GroupDesc* __restrict__ gr
 // point state grows with PPL (x, D and the shapes: one for a Gaussian peak, two
 // for a pseudo-Voigt peak; y too and the deviance's temporaries for Poisson
 // counts); these limits are the largest that compile without spilling on gfx950
-// (pseudo-Voigt with Poisson counts at 32 points per lane spills a few words).
-constexpr int move_min_waves(int peak, int noise, int points) {
+// (pseudo-Voigt with Poisson counts at 32 points per lane spills a few words).  A chain
+// of several wavefronts (the cross-wave reduction) needs a few more registers: one wave
+// less where the limit is 4 or 5.
+constexpr int move_min_waves(int peak, int noise, int points, int wpc) {
+    int w;
     if (noise == SMC_NOISE_GAUSS) {
-        if (peak == SMC_PEAK_GAUSS) return points <= 16 ? 5 : (points <= 20 ? 4 : (points <= 24 ? 3 : 2));
-        return points <= 10 ? 5 : (points <= 16 ? 4 : (points <= 20 ? 3 : 2));
+        if (peak == SMC_PEAK_GAUSS) w = points <= 16 ? 5 : (points <= 20 ? 4 : (points <= 24 ? 3 : 2));
+        else w = points <= 10 ? 5 : (points <= 16 ? 4 : (points <= 20 ? 3 : 2));
+    } else if (peak == SMC_PEAK_GAUSS) {
+        w = points <= 8 ? 5 : (points <= 14 ? 4 : (points <= 20 ? 3 : 2));
+    } else {
+        w = points <= 7 ? 5 : (points <= 12 ? 4 : (points <= 16 ? 3 : 2));
     }
-    if (peak == SMC_PEAK_GAUSS) return points <= 8 ? 5 : (points <= 14 ? 4 : (points <= 20 ? 3 : 2));
-    return points <= 7 ? 5 : (points <= 12 ? 4 : (points <= 16 ? 3 : 2));
+    return wpc > 1 && w >= 4 ? w - 1 : w;
 }
 
 template <int PK, int NZ, int L, int WPC, int PPL>
-__global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL)) k_move(const GroupDesc* __restrict__ groups,
+__global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(const GroupDesc* __restrict__ groups,
                                               const MoveWork* __restrict__ work) {
     using CS = ChainState<PK, NZ, L, WPC, PPL>;
     constexpr int LC = CS::LC;
