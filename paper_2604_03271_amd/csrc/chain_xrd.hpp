@@ -114,25 +114,41 @@ struct XrdChain {
         return __builtin_fmaf(q.aL, l, __builtin_fmaf(q.aG, e, q.c0));
     }
 
+    // The model at a point: the rest of the model Dp plus the term (a peak has no offset).
+    template <bool BG>
+    __device__ __forceinline__ static float model(float Dp, const XrdC& q, float e, float l) {
+        return __builtin_fmaf(q.aL, l, __builtin_fmaf(q.aG, e, BG ? Dp + q.c0 : Dp));
+    }
+
     // Padding points (x = kFarX, y = -1) contribute 0: the deviance maps y < 0 to 0, and
     // their shapes are never evaluated into anything but that term.
-    __device__ __forceinline__ float partial_cached(const XrdC& q) const {
+    template <bool BG>
+    __device__ __forceinline__ float partial_cached_t(const XrdC& q) const {
         float acc = 0.0f;
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) acc += poisson_dev(y[p], D[p] + value(q, S1[p], S2[p]));
+        for (int p = 0; p < PPL; ++p) acc += poisson_dev(y[p], model<BG>(D[p], q, S1[p], S2[p]));
         return acc;
     }
 
-    __device__ __forceinline__ float partial_shape(bool is_bg, const XrdC& q) const {
+    __device__ __forceinline__ float partial_cached(bool is_bg, const XrdC& q) const {
+        return is_bg ? partial_cached_t<true>(q) : partial_cached_t<false>(q);
+    }
+
+    template <bool BG>
+    __device__ __forceinline__ float partial_shape_t(const XrdC& q) const {
         float acc = 0.0f;
         bool bad = false;
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
             float e, l;
-            shape(is_bg, q, p, e, l, bad);
-            acc += poisson_dev(y[p], D[p] + value(q, e, l));
+            shape(BG, q, p, e, l, bad);
+            acc += poisson_dev(y[p], model<BG>(D[p], q, e, l));
         }
         return bad ? __builtin_inff() : acc;
+    }
+
+    __device__ __forceinline__ float partial_shape(bool is_bg, const XrdC& q) const {
+        return is_bg ? partial_shape_t<true>(q) : partial_shape_t<false>(q);
     }
 
     __device__ __forceinline__ void set_shapes(bool is_bg, const XrdC& q) {
@@ -199,7 +215,7 @@ struct XrdChain {
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
             peak_shape(q0, p, S1[p], S2[p], bad);
-            acc += poisson_dev(y[p], D[p] + value(q0, S1[p], S2[p]));
+            acc += poisson_dev(y[p], model<false>(D[p], q0, S1[p], S2[p]));
         }
         return bad ? __builtin_inff() : acc;
     }
@@ -238,7 +254,7 @@ __global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256) k_energy_xrd(con
     if (lane == 0) g.energy[i] = e;
 }
 
-constexpr int xrd_min_waves(int points) { return points <= 6 ? 4 : (points <= 10 ? 3 : 2); }
+constexpr int xrd_min_waves(int points) { return points <= 6 ? 4 : (points <= 14 ? 3 : 2); }
 
 template <int L, int WPC, int PPL>
 __global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256, xrd_min_waves(PPL))
@@ -314,7 +330,7 @@ __global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256, xrd_min_waves(PP
                     if (!prior_in_support(pr, vn)) continue;
                     const XrdC qn = CS::term_consts_with(g, th, k, q, vn);
                     const bool linear = xrd_linear(is_bg, q);
-                    const float part = linear ? cs.partial_cached(qn) : cs.partial_shape(is_bg, qn);
+                    const float part = linear ? cs.partial_cached(is_bg, qn) : cs.partial_shape(is_bg, qn);
                     if (linear) ++my_linear;
                     else ++my_shape;
                     const float En = chain_sum<L, WPC>(part, red, parity);

@@ -162,17 +162,18 @@ __device__ __forceinline__ float bg_eval(float x, const PeakC& q) { return __bui
 // Poisson deviance term f - y + y ln(y/f) = f h((y-f)/f), h(u) = (1+u) ln(1+u) - u,
 // evaluated without cancellation: with v = (y-f)/(y+f) it equals
 // (y-f) v + 2 y v (v^2/3 + v^4/5 + v^6/7 + v^8/9 + ...) for |v| < 0.1 (Loader's
-// saddle-point deviance), and the direct form otherwise.  +inf if f <= 0;
-// 0 for the padding marker y < 0.
+// saddle-point deviance), and the direct form otherwise (y = 0 gives f there: the
+// ratio is floored at 1e-30, whose log times y = 0 is 0).  +inf if f <= 0; 0 for the
+// padding marker y < 0.
 __device__ __forceinline__ float poisson_dev(float y, float f) {
     const float d = y - f;
     const float v = d * __builtin_amdgcn_rcpf(y + f);
     const float v2 = v * v;
     const float series = __builtin_fmaf(
-        2.0f * y * v, v2 * __builtin_fmaf(v2, __builtin_fmaf(v2, __builtin_fmaf(v2, 1.0f / 9.0f, 1.0f / 7.0f), 1.0f / 5.0f),
-                                          1.0f / 3.0f),
+        y * v,
+        v2 * __builtin_fmaf(v2, __builtin_fmaf(v2, __builtin_fmaf(v2, 2.0f / 9.0f, 2.0f / 7.0f), 2.0f / 5.0f), 2.0f / 3.0f),
         d * v);
-    const float direct = y > 0.0f ? __builtin_fmaf(y, fast_ln(y * __builtin_amdgcn_rcpf(f)), -d) : f;
+    const float direct = __builtin_fmaf(y, fast_ln(__builtin_fmaxf(y * __builtin_amdgcn_rcpf(f), 1.0e-30f)), -d);
     const float r = __builtin_fabsf(v) < 0.1f ? series : direct;
     return y < 0.0f ? 0.0f : (f > 0.0f ? r : __builtin_inff());
 }
