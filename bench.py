@@ -78,20 +78,34 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # bench workload (FETCH_SIZE and WRITE_SIZE runs, calibrated with a copy of known size), used
 # only while the move-kernel sources still hash to the value recorded with the counters.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "xps_pv_hbm_traffic.md")
+# Executed VALU and transcendental instructions per launch of the move kernel of the bench
+# workload (rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_VALU_TRANS_F32), under the same rule.
+INSTS_FILE = os.path.join(ROOT, "profiles", "xps_pv_move_instructions.md")
 
 
-def recorded_traffic():
+def _recorded(path, keys):
+    """Machine-readable fields of a profile summary, or None once the hashed sources differ."""
     import hashlib
     try:
-        fields = dict(line.split(" = ", 1) for line in open(TRAFFIC_FILE).read().splitlines() if " = " in line)
+        fields = dict(line.split(" = ", 1) for line in open(path).read().splitlines() if " = " in line)
         h = hashlib.sha256()
         for f in fields["hashed_files"].split():
             h.update(open(os.path.join(ROOT, f), "rb").read())
         if h.hexdigest()[:16] != fields["source_sha256_16"].strip():
             return None
-        return float(fields["traffic_bytes_per_launch"])
+        return [float(fields[k]) for k in keys]
     except (OSError, KeyError, ValueError):
         return None
+
+
+def recorded_traffic():
+    r = _recorded(TRAFFIC_FILE, ["traffic_bytes_per_launch"])
+    return None if r is None else r[0]
+
+
+def recorded_instructions():
+    """(VALU wave-instructions, of which transcendental) per launch, or None."""
+    return _recorded(INSTS_FILE, ["valu_insts_per_launch", "trans_insts_per_launch"])
 
 
 def _cpu_model():
@@ -314,13 +328,24 @@ def main():
     launches = prof1["move_launches"] - prof0["move_launches"]
     move_s = (prof1["move_ms"] - prof0["move_ms"]) / 1e3
     achieved = slots / move_s
-    traffic = recorded_traffic() if args.workload == "xps-pv" and P == 65536 else None
+    bench_shape = args.workload == "xps-pv" and P == 65536 and not args.lanes
+    traffic = recorded_traffic() if bench_shape else None
+    insts = recorded_instructions() if bench_shape else None
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                 "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
                 "kernel": "k_move", "avg_launch_ms": move_s * 1e3 / max(launches, 1),
                 "ops_per_unit": slots / max(move_units, 1), "units_per_launch": move_units / max(launches, 1),
                 "shape_evals": kinds["shape"], "linear_evals": kinds["linear"],
                 "slots_shape": shape_slots, "slots_linear": linear_slots}
+    if insts is not None:
+        # executed instructions (profile counters) over the live launch time: how close the
+        # kernel's instruction issue is to the VALU peak, transcendentals counted once or at
+        # their measured cost
+        valu, trans = insts
+        per_s = 64.0 * launches / move_s
+        roofline["executed"] = {"valu_insts_per_launch": valu, "trans_insts_per_launch": trans,
+                                "frac_issue": valu * per_s / PEAK_LANE_OPS,
+                                "frac_issue_trans_cost": (valu + (TRANS_COST - 1.0) * trans) * per_s / PEAK_LANE_OPS}
 
     out = {
         "metric": "particle*point likelihood evals/s",
