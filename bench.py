@@ -46,6 +46,12 @@ sys.path.insert(0, ROOT)
 SHAPE_VALU = {"pvoigt": 7, "gauss": 5}
 SHAPE_TRANS = {"pvoigt": 2, "gauss": 1}
 LINEAR_VALU = 2
+# Poisson counts (config 3): the point term needs f (the fma that adds the term's value to the
+# rest of the model), ln f and y ln f subtracted and summed (fma, add): a shape proposal is the
+# profile's shape work (pseudo-Voigt 4 VALU + exp2, rcp; Gaussian 3 + exp2), 2 or 1 fma for the
+# value, then 2 VALU + log; a linear proposal 3 VALU + log.
+SHAPE_POISSON = {"pvoigt": (8, 3), "gauss": (6, 2)}
+LINEAR_POISSON = (3, 1)
 # XPS model form (Shirley background, heteroscedastic noise), per point: a centre/width
 # proposal forms the new shapes (4 VALU + exp2, rcp), the new value (2), the change (1),
 # its trapezoid increment and prefix (2), the new background (2), the residual (2) and the
@@ -67,9 +73,13 @@ XPS_LINEAR = (8, 2)
 XRD_PEAK_SHAPE = (21, 6)
 XRD_BG_SHAPE = (8, 3)
 XRD_LINEAR = (4, 1)
-# Issue cost of one transcendental relative to one VALU instruction on gfx950,
-# measured with a throughput microbenchmark (see the design notes).
-TRANS_COST = float(os.environ.get("SMC_TRANS_COST", "2.0"))
+# Issue slots of one transcendental instruction.  Every VALU instruction, transcendental or
+# not, takes one issue slot of its SIMD; a stream of transcendentals alone runs at half rate
+# (a throughput probe on the MI355X), which binds only where they are more than half of the
+# instructions.  The move kernels' mixes are far below that, and their counters agree: the
+# bench move kernel issues VALU instructions at 0.93 of the peak counting each transcendental
+# once (at two slots each the count would exceed the peak).
+TRANS_COST = float(os.environ.get("SMC_TRANS_COST", "1.0"))
 # MI355X: 256 CUs x 4 SIMD x 16 lanes per clock x 2.4 GHz = 39.3e12 lane-instructions/s
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
@@ -227,6 +237,17 @@ def _workload(name, native_options, workloads, particles, lanes=0):
         P, n = particles or 2_000_000, 100
         desc = (f"XPS-like stand-in N={spec.n}, pseudo-Voigt peaks on a dynamic Shirley background, "
                 f"heteroscedastic noise, K={spec.k_min}..{spec.k_max}, P={P} per K, waste-free n={n}")
+    elif name == "config1":
+        spec = workloads.config1(0)
+        P, n = particles or 512, 10
+        desc = f"config 1: N=201, 3 Gaussian peaks, sigma=0.05, K=1..4, P={P} per K, standard n={n}"
+        return spec, native_options(n_particles=P, n_moves=n, waste_free=False, seed=0, profile=True,
+                                    lanes_per_chain=lanes), desc
+    elif name == "config3":
+        spec = workloads.config3(0)
+        P, n = particles or 16384, 16
+        desc = (f"config 3: XRD-like N=4096, 16 pseudo-Voigt peaks + constant background, Poisson counts, "
+                f"K=12..20, P={P} per K, waste-free n={n}")
     elif name.startswith("xrd-"):
         N = int(name.split("-")[1])
         spec = workloads.xrd_powder(n=N, index=0)
@@ -250,7 +271,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="xps-pv",
                     choices=["xps-pv", "paper-k3", "paper-k10", "paper-k30", "xps-shirley", "xrd-1000",
-                             "xrd-5000", "xrd-10000"])
+                             "xrd-5000", "xrd-10000", "config1", "config3"])
     ap.add_argument("--particles", type=int, default=0, help="particles per K (default: the workload's)")
     ap.add_argument("--lanes", type=int, default=0, help="lanes per chain (default: the library's tile rule)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -320,6 +341,9 @@ def main():
         shape_slots = ((1 - fb) * (XRD_PEAK_SHAPE[0] + TRANS_COST * XRD_PEAK_SHAPE[1])
                        + fb * (XRD_BG_SHAPE[0] + TRANS_COST * XRD_BG_SHAPE[1]))
         linear_slots = XRD_LINEAR[0] + TRANS_COST * XRD_LINEAR[1]
+    elif spec.noise_kind == "poisson":
+        shape_slots = SHAPE_POISSON[spec.peak_kind][0] + TRANS_COST * SHAPE_POISSON[spec.peak_kind][1]
+        linear_slots = LINEAR_POISSON[0] + TRANS_COST * LINEAR_POISSON[1]
     else:
         shape_slots = SHAPE_VALU[spec.peak_kind] + TRANS_COST * SHAPE_TRANS[spec.peak_kind]
         linear_slots = LINEAR_VALU
@@ -338,14 +362,12 @@ def main():
                 "shape_evals": kinds["shape"], "linear_evals": kinds["linear"],
                 "slots_shape": shape_slots, "slots_linear": linear_slots}
     if insts is not None:
-        # executed instructions (profile counters) over the live launch time: how close the
-        # kernel's instruction issue is to the VALU peak, transcendentals counted once or at
-        # their measured cost
+        # executed VALU instructions (profile counters, transcendentals included) over the live
+        # launch time: how close the kernel's instruction issue is to the VALU peak
         valu, trans = insts
         per_s = 64.0 * launches / move_s
         roofline["executed"] = {"valu_insts_per_launch": valu, "trans_insts_per_launch": trans,
-                                "frac_issue": valu * per_s / PEAK_LANE_OPS,
-                                "frac_issue_trans_cost": (valu + (TRANS_COST - 1.0) * trans) * per_s / PEAK_LANE_OPS}
+                                "frac_issue": valu * per_s / PEAK_LANE_OPS}
 
     out = {
         "metric": "particle*point likelihood evals/s",
@@ -370,7 +392,8 @@ def main():
         "roofline": roofline,
     }
     if not args.no_plain:
-        sp = native.Sampler(spec, native.options(n_particles=P, n_moves=n, waste_free=True, seed=0, plain=True))
+        sp = native.Sampler(spec, native.options(n_particles=P, n_moves=n, waste_free=bool(opt.waste_free), seed=0,
+                                                 plain=True, lanes_per_chain=args.lanes))
         torch.cuda.synchronize()
         ts = time.perf_counter()
         sp.reset(1).run()
