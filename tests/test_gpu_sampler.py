@@ -183,6 +183,25 @@ def test_config1_parity_with_reference(orc):
     assert np.argmax(np.mean(g, 0)) == np.argmax(np.mean(o, 0))
 
 
+def test_config2_parity_with_reference(orc):
+    """Config-2 shape (N=1001, pseudo-Voigt + linear background, waste-free n=16) at a reduced
+    P = 4096 and K = 4..5 (clearly separated evidences), 10 seeds on both sides.  (Config 3's
+    reference run takes minutes per K even at P = 512; its stage is checked at full size.)"""
+    spec = W.config2(0)
+    spec.k_min, spec.k_max = 4, 5
+    P = 4096
+    opr = orc.Problem(spec)
+    g, o = [], []
+    for seed in range(1, 11):
+        say("e2e config2 seed", seed)
+        g.append(_gpu_logz(spec, seed, n_particles=P, n_moves=16, waste_free=True))
+        o.append([orc.run(opr, K, P, 16, True, seed + 1000, spec.uid).log_evidence for K in (4, 5)])
+    d, se = _stat_parity(g, o)
+    say("config2 diff", d, "se", se, "gpu", np.mean(g, 0), "ref", np.mean(o, 0))
+    assert np.all(np.abs(d) <= 3 * se + 1e-9) and np.all(np.abs(d) <= 0.05 + 3 * se), (d, se)
+    assert np.argmax(np.mean(g, 0)) == np.argmax(np.mean(o, 0))
+
+
 def test_sampler_trace_invariants():
     spec = W.config1(1)
     say("trace invariants")
