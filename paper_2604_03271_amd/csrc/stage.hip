@@ -712,44 +712,44 @@ __global__ void __launch_bounds__(kChunkThreads) k_st_resample(const GroupDesc* 
     }
 }
 
-// Random-walk scales s_j = lambda_j * sd_j over the resampled states (one wave per component).
-__global__ void __launch_bounds__(kChunkThreads) k_st_steps(const GroupDesc* __restrict__ groups, int jblocks) {
-    const int gi = blockIdx.x / jblocks, jb = blockIdx.x % jblocks;
+// Random-walk scales s_j = lambda_j * sd_j over the resampled states: one 256-thread
+// workgroup per (group, component) (a fixed shape, so every path sums in the same order
+// and gives the same bits), two passes (the mean, then the squared deviations) in FP64 with
+// four accumulators per thread to keep several loads in flight.
+__global__ void __launch_bounds__(kChunkThreads) k_st_steps(const GroupDesc* __restrict__ groups, int dmax) {
+    __shared__ double red[1][kChunkWaves];
+    const int gi = blockIdx.x / dmax, j = blockIdx.x % dmax;
     const GroupDesc& g = groups[gi];
-    const int lane = threadIdx.x & 63;
-    const int j = jb * kChunkWaves + static_cast<int>(threadIdx.x >> 6);
     if (g.st->done || j >= g.d) return;
     if (g.prior[j].kind == SMC_PRIOR_FIXED) {
-        if (lane == 0) g.step[j] = 0.0f;
+        if (threadIdx.x == 0) g.step[j] = 0.0f;
         return;
     }
     const int M = g.M;
     const float* col = g.start + (size_t)j * M;
-    // four independent accumulators per lane keep several loads in flight
+    constexpr int kStride = 4 * kChunkThreads;
     double acc4[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int m0 = lane; m0 < M; m0 += 256)
+    for (int m0 = threadIdx.x; m0 < M; m0 += kStride)
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-            if (m0 + 64 * u < M) acc4[u] += col[m0 + 64 * u];
-    double sum = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
-    const double mean = sum / M;
+            if (m0 + kChunkThreads * u < M) acc4[u] += col[m0 + kChunkThreads * u];
+    double v[1] = {(acc4[0] + acc4[1]) + (acc4[2] + acc4[3])};
+    chunk_block_sum<1>(v, red);
+    const double mean = v[0] / M;
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc4[u] = 0.0;
-    for (int m0 = lane; m0 < M; m0 += 256)
+    for (int m0 = threadIdx.x; m0 < M; m0 += kStride)
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-            if (m0 + 64 * u < M) {
-                const double dd = col[m0 + 64 * u] - mean;
+            if (m0 + kChunkThreads * u < M) {
+                const double dd = col[m0 + kChunkThreads * u] - mean;
                 acc4[u] += dd * dd;
             }
-    double ss = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
-    const double sd = sqrt(ss / M);
+    v[0] = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
+    chunk_block_sum<1>(v, red);
+    const double sd = sqrt(v[0] / M);
     const double fl = 1e-12 * (fabs(mean) + 1.0);
-    if (lane == 0) g.step[j] = static_cast<float>(g.lambda[j] * (sd > fl ? sd : fl));
+    if (threadIdx.x == 0) g.step[j] = static_cast<float>(g.lambda[j] * (sd > fl ? sd : fl));
 }
 
 // ------------------------------------------------------------------ hook kernels
@@ -804,8 +804,8 @@ hipError_t launch_stage(const StageLaunch& L, hipStream_t s) {
     const int mblocks = (L.max_m + kChunkThreads - 1) / kChunkThreads;
     hipLaunchKernelGGL(k_st_resample, dim3(L.n_groups * mblocks), dim3(kChunkThreads), 0, s, L.groups, mblocks,
                        int64_t{-1}, static_cast<int32_t*>(nullptr));
-    const int jblocks = (std::max(L.max_d, 1) + kChunkWaves - 1) / kChunkWaves;
-    hipLaunchKernelGGL(k_st_steps, dim3(L.n_groups * jblocks), dim3(kChunkThreads), 0, s, L.groups, jblocks);
+    const int dmax = std::max(L.max_d, 1);
+    hipLaunchKernelGGL(k_st_steps, dim3(L.n_groups * dmax), dim3(kChunkThreads), 0, s, L.groups, dmax);
     return hipGetLastError();
 }
 
