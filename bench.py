@@ -274,6 +274,7 @@ def main():
                              "xrd-5000", "xrd-10000", "config1", "config3"])
     ap.add_argument("--particles", type=int, default=0, help="particles per K (default: the workload's)")
     ap.add_argument("--lanes", type=int, default=0, help="lanes per chain (default: the library's tile rule)")
+    ap.add_argument("--tune", action="store_true", help="lanes per chain from the library's autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--batch", type=int, default=0, help="also run the config-4 batch with this many spectra")
@@ -301,6 +302,12 @@ def main():
         del src, dst
     spec, opt, desc = _workload(args.workload, native.options, workloads, args.particles, args.lanes)
     P, n = opt.n_particles, opt.n_moves
+    tuned = None
+    if args.tune:
+        lanes, ns = native.smc_tune_lanes(native.Problem(spec), opt, 2)
+        opt.lanes_per_chain = args.lanes = lanes
+        tuned = {"lanes_per_chain": lanes, "move_ns_per_eval": ns}
+        progress(f"autotuner: {lanes} lanes per chain, {ns * 1e3:.4g} ps of move time per particle*point evaluation")
     ks = range(spec.k_min, spec.k_max + 1)
     s = native.Sampler(spec, opt)
     for w in range(args.warmup):
@@ -391,6 +398,8 @@ def main():
         "best_k": int(np.argmax(np.mean(logz, 0)) + spec.k_min),
         "roofline": roofline,
     }
+    if tuned is not None:
+        out["tuned"] = tuned
     if not args.no_plain:
         sp = native.Sampler(spec, native.options(n_particles=P, n_moves=n, waste_free=bool(opt.waste_free), seed=0,
                                                  plain=True, lanes_per_chain=args.lanes))

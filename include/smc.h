@@ -165,6 +165,19 @@ smc_status smc_evaluation_kinds(const smc_ctx* ctx, uint64_t* out);
  * on the context's stream. */
 smc_status smc_profile(const smc_ctx* ctx, double* out);
 
+/* Tile autotuner: runs `stages` (1..64) tempering stages of this problem with every lane
+ * count its model family supports and that holds its N points (16, 32, 64, 256; 512 for
+ * XRD), times the move kernel with HIP events, and writes the lane count with the least move
+ * time per particle*point evaluation to *lanes_out (and that time, ns, to *ns_per_eval_out
+ * if not NULL).  Pass it as options.lanes_per_chain.  Results are cached per process and
+ * device by the problem's shape and the options' P, n and mode, so a second call with the
+ * same shape returns at once.  Different lane counts split the points differently, so their
+ * FP32 energies differ by rounding: the default rule (lanes_per_chain = 0) is the one that
+ * gives the same bits on every machine.  Allocates and frees one context per candidate.
+ * Errors: SMC_EINVAL (bad problem or options, no lane count fits), SMC_EDEVICE, SMC_ENOMEM. */
+smc_status smc_tune_lanes(const smc_problem* prob, const smc_options* opt, int32_t stages, int32_t* lanes_out,
+                          double* ns_per_eval_out);
+
 /* log Z_K for K = k_min .. k_min + cap - 1 into logz (host, FP64), with every constant of
  * the likelihood included, so F(K) = -logz[K - k_min].  Returns SMC_ESTATE (and the partial
  * estimates) if some K has not finished. */

@@ -10,9 +10,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "host_common.hpp"
@@ -865,4 +867,86 @@ extern "C" void smc_free(smc_ctx* c) {
     if (c->dmem) hipFree(c->dmem);
     if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
     delete c;
+}
+
+// ------------------------------------------------------------------ tile tuner
+//
+// Times the move kernel of every lane configuration that has kernels for the problem's
+// model family and holds its N points, on this device, and keeps the fastest per problem
+// shape.  Each candidate runs `stages` tempering stages of the problem itself (stage 0
+// included) with HIP-event profiling; the cost is the move time per particle*point
+// evaluation, so candidates that take slightly different trajectories compare fairly.
+
+namespace {
+
+struct TuneKey {
+    int32_t peak, bg, noise, n, k_min, k_max, P, n_moves, waste_free, stages, device;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(peak, bg, noise, n, k_min, k_max, P, n_moves, waste_free, stages, device) <
+               std::tie(o.peak, o.bg, o.noise, o.n, o.k_min, o.k_max, o.P, o.n_moves, o.waste_free, o.stages,
+                        o.device);
+    }
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int32_t, double>> g_tune_cache;
+
+}  // namespace
+
+extern "C" smc_status smc_tune_lanes(const smc_problem* prob, const smc_options* opt, int32_t stages,
+                                     int32_t* lanes_out, double* ns_per_eval_out) {
+    if (!prob || !opt || !lanes_out || stages < 1 || stages > 64) return SMC_EINVAL;
+    smc_options base = *opt;
+    base.lanes_per_chain = 0;
+    const smc_status vst = validate(prob, &base);
+    if (vst != SMC_OK) return vst;
+    if (!device_ok()) return SMC_EDEVICE;
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return SMC_EDEVICE;
+    const TuneKey key{prob->peak_kind, prob->bg_kind, prob->noise_kind, prob->n_points, prob->k_min, prob->k_max,
+                      opt->n_particles, opt->n_moves, opt->waste_free, stages, device};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        const auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            *lanes_out = it->second.first;
+            if (ns_per_eval_out) *ns_per_eval_out = it->second.second;
+            return SMC_OK;
+        }
+    }
+    int32_t best = 0;
+    double best_ns = INFINITY;
+    for (int lc = 0; lc < kNumLaneCfg; ++lc) {
+        smc_options o = base;
+        o.lanes_per_chain = kLanesOf[lc];
+        o.profile = 1;
+        if (validate(prob, &o) != SMC_OK) continue;   // a lane count this family does not run
+        smc_ctx* c = nullptr;
+        smc_status st = smc_init(&c, prob, &o);
+        if (st == SMC_EINVAL) continue;               // no tile holds N at this lane count
+        if (st != SMC_OK) return st;
+        uint64_t e0 = 0, e1 = 0;
+        double prof[4] = {0.0, 0.0, 0.0, 0.0};
+        int32_t done = 0;
+        st = smc_evaluations(c, &e0);
+        for (int s = 0; s < stages && st == SMC_OK && !done; ++s) st = smc_step(c, &done);
+        if (st == SMC_OK) st = smc_profile(c, prof);
+        if (st == SMC_OK) st = smc_evaluations(c, &e1);
+        smc_free(c);
+        if (st != SMC_OK) return st;
+        if (e1 <= e0 || prof[1] < 1.0) continue;
+        const double ns = prof[0] * 1e6 / (static_cast<double>(e1 - e0) * prob->n_points);
+        if (ns < best_ns) {
+            best_ns = ns;
+            best = kLanesOf[lc];
+        }
+    }
+    if (best == 0) return SMC_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = {best, best_ns};
+    }
+    *lanes_out = best;
+    if (ns_per_eval_out) *ns_per_eval_out = best_ns;
+    return SMC_OK;
 }

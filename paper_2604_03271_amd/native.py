@@ -96,6 +96,7 @@ _SIGNATURES = {
     "smc_reset": (c_i32, [c_vp, c_u64]),
     "smc_evaluations": (c_i32, [c_vp, P(c_u64)]),
     "smc_profile": (c_i32, [c_vp, P(c_d)]),
+    "smc_tune_lanes": (c_i32, [P(smc_problem), P(smc_options), c_i32, P(c_i32), P(c_d)]),
     "smc_evaluation_kinds": (c_i32, [c_vp, P(c_u64)]),
     "smc_log_evidence": (c_i32, [c_vp, P(c_d), c_i32]),
     "smc_stage_info": (c_i32, [c_vp, c_i32, P(c_i32), P(c_d), P(c_d), P(c_d)]),
@@ -280,6 +281,16 @@ def smc_profile(ctx) -> dict:
     out = np.zeros(4)
     check(lib().smc_profile(ctx, _pd(out)), "smc_profile")
     return {"move_ms": out[0], "move_launches": int(out[1]), "stage_ms": out[2], "stage_launches": int(out[3])}
+
+
+def smc_tune_lanes(problem: "Problem", opt, stages: int = 2):
+    """(lanes per chain, move ns per particle*point evaluation) of the fastest lane count for
+    this problem shape on the current device (cached per process)."""
+    lanes = c_i32()
+    ns = c_d()
+    check(lib().smc_tune_lanes(problem.ref, ctypes.byref(opt), stages, ctypes.byref(lanes), ctypes.byref(ns)),
+          "smc_tune_lanes")
+    return int(lanes.value), float(ns.value)
 
 
 def smc_log_evidence(ctx, n: int, allow_partial: bool = False) -> np.ndarray:

@@ -186,3 +186,15 @@ def test_xrd_point_limit_and_short_mu_ref():
     assert _init_status(W.xrd_powder(n=10241)) == native.SMC_EINVAL
     with pytest.raises(ValueError):
         native.Problem(_xrd(mu_ref=[27.4, 25.3]))
+
+
+def test_tuner_rejects_bad_arguments_before_the_device():
+    L = native.lib()
+    pr = native.Problem(W.config1(0))
+    o = native.options()
+    lanes = ctypes.c_int32()
+    assert L.smc_tune_lanes(None, ctypes.byref(o), 2, ctypes.byref(lanes), None) == native.SMC_EINVAL
+    assert L.smc_tune_lanes(pr.ref, ctypes.byref(o), 0, ctypes.byref(lanes), None) == native.SMC_EINVAL
+    assert L.smc_tune_lanes(pr.ref, ctypes.byref(o), 2, None, None) == native.SMC_EINVAL
+    bad = native.options(n_particles=1)
+    assert L.smc_tune_lanes(pr.ref, ctypes.byref(bad), 2, ctypes.byref(lanes), None) == native.SMC_EINVAL

@@ -265,3 +265,24 @@ def test_evaluation_kinds():
     frac = k["linear"] / (k["shape"] + k["linear"])
     assert 0.3 < frac < 0.7, frac
     s.close()
+
+
+@pytest.mark.parametrize("make,allowed", [(lambda: W.config2(0), {16, 32, 64, 256}),
+                                          (lambda: W.xrd_powder(n=1000), {64, 256, 512})])
+def test_tuner_picks_a_supported_lane_count(make, allowed):
+    """The autotuner returns a lane count that holds the problem, caches it, and a run with it
+    gives finite evidences."""
+    import time
+    spec = make()
+    opt = native.options(seed=1, n_particles=8192, n_moves=8, waste_free=True)
+    say("tune", spec.n)
+    lanes, ns = native.smc_tune_lanes(native.Problem(spec), opt, stages=2)
+    assert lanes in allowed and 0 < ns < 1e3, (lanes, ns)
+    t0 = time.perf_counter()
+    assert native.smc_tune_lanes(native.Problem(spec), opt, stages=2) == (lanes, ns)   # cached
+    assert time.perf_counter() - t0 < 0.05
+    s = native.Sampler(spec, native.options(seed=1, n_particles=8192, n_moves=8, waste_free=True, lanes_per_chain=lanes))
+    for _ in range(3):
+        s.step()
+    assert all(np.isfinite(s.stage_info(K)[2]) for K in range(spec.k_min, spec.k_max + 1))
+    s.close()
