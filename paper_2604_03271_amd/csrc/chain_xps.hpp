@@ -13,12 +13,16 @@
 // its values (shapes re-evaluated for a centre or width, cached for an amplitude or
 // a Gaussian fraction), the change of C by the scan, the new background and the
 // noise terms.  A background proposal (a or b) needs no scan.  Moving to the next
-// peak only evaluates its shapes.  The cache is rebuilt every kRebuildEvery sweeps.
+// peak only evaluates its shapes.  The cache is rebuilt every kXpsRebuildEvery sweeps.
 #pragma once
 
 #include "chain.hpp"
 
 namespace smc {
+
+// The prefix integrals of the Shirley cache take more incremental updates per sweep than
+// the plain residual cache, so they are rebuilt from the parameters more often.
+constexpr int kXpsRebuildEvery = 4;
 
 // Inclusive prefix of v over the L lanes of each chain inside one wavefront (L = 16,
 // 32, 64; rows of 16 lanes), and the chain's total in every lane of the chain.
@@ -304,7 +308,7 @@ __global__ void __launch_bounds__(256, xps_min_waves(PPL)) k_move_xps(const Grou
         }
         __syncthreads();
         if (active) {
-            if (t % kRebuildEvery == 0) E = group_sum<L>(cs.rebuild(g, th));
+            if (t % kXpsRebuildEvery == 0) E = group_sum<L>(cs.rebuild(g, th));
             else cs.set_shapes(peak_consts<SMC_PEAK_PVOIGT>(th));
             for (int k = 0; k <= g.K; ++k) {
                 const bool is_bg = k == g.K;
