@@ -180,7 +180,7 @@ struct PoolView {
             b.work_off = static_cast<int>(work.size());
             build_work(gs, chains, b.tile, work);
             b.work_cnt = static_cast<int>(work.size()) - b.work_off;
-            b.lds_move = move_lds_bytes(b.tile, dmax);
+            b.lds_move = move_lds_bytes(b.tile, dmax, b.pk, b.nz);
             b.lds_energy = energy_lds_bytes(b.tile, dmax);
             buckets.push_back(b);
         }

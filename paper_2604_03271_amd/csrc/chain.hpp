@@ -138,6 +138,35 @@ struct ChainState {
         return acc;
     }
 
+    // A centre or width proposal that also leaves its shapes at sl[p * LC] (this lane's
+    // entries of its chain's LDS area: one float, or a float2 for a pseudo-Voigt peak).
+    __device__ __forceinline__ float partial_shape_store(const PeakC& q, float* sl) const {
+        float acc = 0.0f;
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            float e, l;
+            shape_at(q, p, e, l);
+            if constexpr (kPV) reinterpret_cast<float2*>(sl)[p * LC] = make_float2(e, l);
+            else sl[p * LC] = e;
+            acc += point_term(add_peak(D[p], kInclude, q, e, l), p);
+        }
+        return acc;
+    }
+
+    // An accepted proposal whose shapes partial_shape_store left in LDS.
+    __device__ __forceinline__ void load_shapes(const float* sl) {
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            if constexpr (kPV) {
+                const float2 v = reinterpret_cast<const float2*>(sl)[p * LC];
+                S1[p] = v.x;
+                S2[p] = v.y;
+            } else {
+                S1[p] = sl[p * LC];
+            }
+        }
+    }
+
     // An accepted centre or width: the cached shapes follow the new constants.
     __device__ __forceinline__ void accept_shape(const PeakC& q) {
 #pragma unroll
@@ -313,6 +342,10 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(
     uint32_t* accc = reinterpret_cast<uint32_t*>(body + CPW * 3 * d);
     float* red = body + CPW * 3 * d + d;
     uint32_t* nevals = reinterpret_cast<uint32_t*>(red + 2 * WPC);   // [0] shape, [1] linear
+    // the proposal's shapes, [chain slot][point][lane], 8-byte aligned after the above
+    constexpr int kSB = move_shape_lds_bytes(PK, NZ, PPL);
+    float* shp = lds + ((4 * d + CPW * 3 * d + d + 2 * WPC + 2 + 1) & ~1);
+    float* my_shp = shp + (kSB / 4) * (slot * PPL * LC + lane);
 
     const bool active = slot < w.nchains;
     const int m = w.chain0 + slot;
@@ -381,6 +414,8 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(
                         part = cs.partial_bg(qn);
                     } else if (linear) {
                         part = cs.partial_linear(qn);
+                    } else if constexpr (kSB > 0) {
+                        part = cs.partial_shape_store(qn, my_shp);
                     } else {
                         part = cs.partial_shape(qn);
                     }
@@ -391,7 +426,10 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(
                     const float log_alpha = -beta * (En - E) + prior_log_ratio(pr, vn, vo);
                     if (lnu[j] < log_alpha) {
                         E = En;
-                        if (!linear) cs.accept_shape(qn);
+                        if (!linear) {
+                            if constexpr (kSB > 0) cs.load_shapes(my_shp);
+                            else cs.accept_shape(qn);
+                        }
                         th[j] = vn;
                         if (lane == 0) atomicAdd(&accc[j], 1u);
                     }

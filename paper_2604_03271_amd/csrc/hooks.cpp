@@ -266,7 +266,7 @@ extern "C" smc_status smc_kernel_move(const smc_problem* prob, int32_t K, const 
     h.g.acc = acc;
     if ((st = upload_desc(h, s)) != SMC_OK) return st;
     const void* fn = kernels().move[h.g.peak_kind][h.g.noise_kind][h.tile.lc][h.tile.pi];
-    if (launch_tiled(fn, h.tile, h.n_work, move_lds_bytes(h.tile, h.g.d), h.d_group, h.d_work, s) != hipSuccess)
+    if (launch_tiled(fn, h.tile, h.n_work, move_lds_bytes(h.tile, h.g.d, h.g.peak_kind, h.g.noise_kind), h.d_group, h.d_work, s) != hipSuccess)
         return SMC_EDEVICE;
     return finish(s);
 }

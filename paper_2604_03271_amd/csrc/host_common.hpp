@@ -66,7 +66,7 @@ bool xps_model(const smc_problem& p);
 void model_consts(const smc_problem& p, int K, GroupDesc& g);
 Tile choose_tile(const smc_problem& p, int64_t chains, int forced_lanes);
 bool tile_has_kernels(const smc_problem& p, const Tile& t);
-size_t move_lds_bytes(const Tile& t, int d);
+size_t move_lds_bytes(const Tile& t, int d, int peak_kind, int noise_kind);
 size_t energy_lds_bytes(const Tile& t, int d);
 void build_work(const std::vector<int>& groups, const std::vector<int>& chains_of, const Tile& t,
                 std::vector<MoveWork>& out);

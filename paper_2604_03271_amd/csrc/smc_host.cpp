@@ -224,9 +224,12 @@ bool tile_has_kernels(const smc_problem& p, const Tile& t) {
 // two evaluation counters.
 static size_t reduce_floats(const Tile& t) { return 2 * static_cast<size_t>(t.lanes > 64 ? t.lanes / 64 : 1) + 2; }
 
-size_t move_lds_bytes(const Tile& t, int d) {
+size_t move_lds_bytes(const Tile& t, int d, int peak_kind, int noise_kind) {
     const int cpw = tile_chains_per_wg(t);
-    return sizeof(DevPrior) * d + sizeof(float) * (static_cast<size_t>(cpw) * 3 * d + d + reduce_floats(t));
+    size_t b = sizeof(DevPrior) * d + sizeof(float) * (static_cast<size_t>(cpw) * 3 * d + d + reduce_floats(t));
+    const int sb = move_shape_lds_bytes(peak_kind, noise_kind, t.ppl);
+    if (sb > 0) b = ((b + 7) & ~static_cast<size_t>(7)) + static_cast<size_t>(sb) * tile_threads(t) * t.ppl;
+    return b;
 }
 
 size_t energy_lds_bytes(const Tile& t, int d) {
@@ -579,7 +582,7 @@ extern "C" smc_status smc_init(smc_ctx** out, const smc_problem* prob, const smc
     if (!c->d_work || !c->d_init_work) return ctx_fail(c, SMC_ENOMEM);
     int dmax = 1;
     for (const GroupDesc& g : c->groups) dmax = std::max(dmax, g.d);
-    c->lds_move = move_lds_bytes(c->tile, dmax);
+    c->lds_move = move_lds_bytes(c->tile, dmax, prob->peak_kind, prob->noise_kind);
     c->lds_energy = energy_lds_bytes(c->tile, dmax);
 
     c->states.assign(c->ng, GroupState{});
