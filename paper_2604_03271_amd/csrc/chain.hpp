@@ -343,7 +343,7 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(
     float* red = body + CPW * 3 * d + d;
     uint32_t* nevals = reinterpret_cast<uint32_t*>(red + 2 * WPC);   // [0] shape, [1] linear
     // the proposal's shapes, [chain slot][point][lane], 8-byte aligned after the above
-    constexpr int kSB = move_shape_lds_bytes(PK, NZ, PPL);
+    constexpr int kSB = move_shape_lds_bytes(PK, NZ, PPL, 256);
     float* shp = lds + ((4 * d + CPW * 3 * d + d + 2 * WPC + 2 + 1) & ~1);
     float* my_shp = shp + (kSB / 4) * (slot * PPL * LC + lane);
 

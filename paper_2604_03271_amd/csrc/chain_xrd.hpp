@@ -151,6 +151,35 @@ struct XrdChain {
         return is_bg ? partial_shape_t<true>(q) : partial_shape_t<false>(q);
     }
 
+    // The same, leaving the proposal's shapes at sl[p * LC] (float2 units: this lane's
+    // entries of its chain's LDS area) for an accept.
+    template <bool BG>
+    __device__ __forceinline__ float partial_shape_store_t(const XrdC& q, float2* sl) const {
+        float acc = 0.0f;
+        bool bad = false;
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            float e, l;
+            shape(BG, q, p, e, l, bad);
+            sl[p * LC] = make_float2(e, l);
+            acc += poisson_dev(y[p], model<BG>(D[p], q, e, l));
+        }
+        return bad ? __builtin_inff() : acc;
+    }
+
+    __device__ __forceinline__ float partial_shape_store(bool is_bg, const XrdC& q, float2* sl) const {
+        return is_bg ? partial_shape_store_t<true>(q, sl) : partial_shape_store_t<false>(q, sl);
+    }
+
+    __device__ __forceinline__ void load_shapes(const float2* sl) {
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            const float2 v = sl[p * LC];
+            S1[p] = v.x;
+            S2[p] = v.y;
+        }
+    }
+
     __device__ __forceinline__ void set_shapes(bool is_bg, const XrdC& q) {
         bool bad = false;
 #pragma unroll
@@ -279,6 +308,10 @@ __global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256, xrd_min_waves(PP
     uint32_t* accc = reinterpret_cast<uint32_t*>(body + CPW * 3 * d);
     float* red = body + CPW * 3 * d + d;
     uint32_t* nevals = reinterpret_cast<uint32_t*>(red + 2 * WPC);
+    // the proposal's shapes, [chain slot][point][lane] float2, 8-byte aligned after the above
+    constexpr int kSB = move_shape_lds_bytes(SMC_PEAK_XRD, SMC_NOISE_POISSON, PPL, TPB);
+    float2* my_shp = reinterpret_cast<float2*>(lds + ((4 * d + CPW * 3 * d + d + 2 * WPC + 2 + 1) & ~1)) +
+                     (slot * PPL * LC + lane);
 
     const bool active = slot < w.nchains;
     const int m = w.chain0 + slot;
@@ -330,14 +363,20 @@ __global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256, xrd_min_waves(PP
                     if (!prior_in_support(pr, vn)) continue;
                     const XrdC qn = CS::term_consts_with(g, th, k, q, vn);
                     const bool linear = xrd_linear(is_bg, q);
-                    const float part = linear ? cs.partial_cached(is_bg, qn) : cs.partial_shape(is_bg, qn);
+                    float part;
+                    if (linear) part = cs.partial_cached(is_bg, qn);
+                    else if constexpr (kSB > 0) part = cs.partial_shape_store(is_bg, qn, my_shp);
+                    else part = cs.partial_shape(is_bg, qn);
                     if (linear) ++my_linear;
                     else ++my_shape;
                     const float En = chain_sum<L, WPC>(part, red, parity);
                     const float log_alpha = -beta * (En - E) + prior_log_ratio(pr, vn, vo);
                     if (lnu[j] < log_alpha) {
                         E = En;
-                        if (!linear) cs.set_shapes(is_bg, qn);
+                        if (!linear) {
+                            if constexpr (kSB > 0) cs.load_shapes(my_shp);
+                            else cs.set_shapes(is_bg, qn);
+                        }
                         th[j] = vn;
                         if (lane == 0) atomicAdd(&accc[j], 1u);
                     }

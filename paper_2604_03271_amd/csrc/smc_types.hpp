@@ -83,14 +83,16 @@ struct GroupDesc {
     const float* mu_ref;        // XRD peaks: reference positions [K]
 };
 
-// Bytes of LDS per lane and point where the move kernel of the Gaussian / pseudo-Voigt
-// families keeps the shapes of the current proposal (an accepted centre or width then copies
-// them instead of evaluating them again): 4 (one shape) or 8 (two), or 0 where a 256-thread
-// workgroup would need more than 32 KB for them.  XPS and XRD kernels keep none.
-constexpr int move_shape_lds_bytes(int peak_kind, int noise_kind, int ppl) {
-    if (peak_kind == SMC_PEAK_XRD || noise_kind == SMC_NOISE_HETERO) return 0;
-    const int b = peak_kind == SMC_PEAK_PVOIGT ? 8 : 4;
-    return ppl * 256 * b <= 32768 ? b : 0;
+// Bytes of LDS per lane and point where a move kernel keeps the shapes of the current
+// proposal (an accepted shape proposal then copies them instead of evaluating them again):
+// 4 (one shape: Gaussian peak) or 8 (two: pseudo-Voigt, XRD), or 0 where a workgroup of
+// `threads` would need more than 32 KB (40 KB for the XRD kernels, whose occupancy is
+// register-bound at 2-3 waves per SIMD there) for them.  The XPS kernels keep none.
+constexpr int move_shape_lds_bytes(int peak_kind, int noise_kind, int ppl, int threads) {
+    if (noise_kind == SMC_NOISE_HETERO) return 0;
+    const int b = peak_kind == SMC_PEAK_GAUSS ? 4 : 8;
+    const int limit = peak_kind == SMC_PEAK_XRD ? 40960 : 32768;
+    return ppl * threads * b <= limit ? b : 0;
 }
 
 // One workgroup of the move / energy kernels: chains [chain0, chain0 + nchains) of a group.
