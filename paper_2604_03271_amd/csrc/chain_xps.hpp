@@ -101,6 +101,15 @@ struct XpsChain {
         for (int p = 0; p < PPL; ++p) shape_at(q, p, S1[p], S2[p]);
     }
 
+    __device__ __forceinline__ void load_shapes(const float2* sl) {
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            const float2 v = sl[p * L];
+            S1[p] = v.x;
+            S2[p] = v.y;
+        }
+    }
+
     // Twice the trapezoid increments of v over this lane's points, prefix-summed over the
     // chain into out (inclusive); returns the chain total.  The point widths are formed from
     // copies of x that an empty asm makes opaque, so that the compiler does not hoist them
@@ -174,13 +183,16 @@ struct XpsChain {
 
     // Proposal changing the current peak from qo to qn: d = change of the peak's values,
     // dC = change of C, dCN = change of C_N.  Returns the energy share.
-    template <bool kShape>
+    // With kStore a shape proposal also leaves its shapes at sl[p * L] (float2 units: this
+    // lane's entries of its chain's LDS area) for an accept.
+    template <bool kShape, bool kStore = false>
     __device__ __forceinline__ float partial_peak(const PeakC& qo, const PeakC& qn, const float* hn, float a, float b,
-                                                  float* d, float* dC, float& dCN) const {
+                                                  float* d, float* dC, float& dCN, float2* sl = nullptr) const {
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
             float e = S1[p], l = S2[p];
             if constexpr (kShape) shape_at(qn, p, e, l);
+            if constexpr (kShape && kStore) sl[p * L] = make_float2(e, l);
             d[p] = value(qn, e, l) - value(qo, S1[p], S2[p]);
         }
         dCN = integrate(d, dC);
@@ -273,6 +285,9 @@ __global__ void __launch_bounds__(256, xps_min_waves(PPL)) k_move_xps(const Grou
     float* lnu = inc + d;
     uint32_t* accc = reinterpret_cast<uint32_t*>(body + CPW * 3 * d);
     uint32_t* nevals = reinterpret_cast<uint32_t*>(body + CPW * 3 * d + d + 2);   // [0] shape, [1] linear
+    // the proposal's shapes, [chain slot][point][lane] float2, 8-byte aligned after the above
+    constexpr int kSB = move_shape_lds_bytes(SMC_PEAK_PVOIGT, SMC_NOISE_HETERO, PPL, 256);
+    float2* my_shp = reinterpret_cast<float2*>(lds + ((4 * d + CPW * 3 * d + d + 4 + 1) & ~1)) + (slot * PPL * L + lane);
 
     const bool active = slot < w.nchains;
     const int m = w.chain0 + slot;
@@ -336,7 +351,7 @@ __global__ void __launch_bounds__(256, xps_min_waves(PPL)) k_move_xps(const Grou
                         qn = peak_consts<SMC_PEAK_PVOIGT>(tmp);
                         const float a = th[jbg], b = th[jbg + 1];
                         if (linear) part = cs.template partial_peak<false>(qo, qn, g.hn, a, b, dd, dC, dCN);
-                        else part = cs.template partial_peak<true>(qo, qn, g.hn, a, b, dd, dC, dCN);
+                        else part = cs.template partial_peak<true, (kSB > 0)>(qo, qn, g.hn, a, b, dd, dC, dCN, my_shp);
                     }
                     if (linear) ++my_linear;
                     else ++my_shape;
@@ -346,7 +361,10 @@ __global__ void __launch_bounds__(256, xps_min_waves(PPL)) k_move_xps(const Grou
                         E = En;
                         if (!is_bg) {
                             cs.accept_peak(dd, dC, dCN);
-                            if (!linear) cs.set_shapes(qn);
+                            if (!linear) {
+                                if constexpr (kSB > 0) cs.load_shapes(my_shp);
+                                else cs.set_shapes(qn);
+                            }
                         }
                         th[j] = vn;
                         if (lane == 0) atomicAdd(&accc[j], 1u);

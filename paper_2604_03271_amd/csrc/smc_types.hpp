@@ -87,9 +87,9 @@ struct GroupDesc {
 // proposal (an accepted shape proposal then copies them instead of evaluating them again):
 // 4 (one shape: Gaussian peak) or 8 (two: pseudo-Voigt, XRD), or 0 where a workgroup of
 // `threads` would need more than 32 KB (40 KB for the XRD kernels, whose occupancy is
-// register-bound at 2-3 waves per SIMD there) for them.  The XPS kernels keep none.
+// register-bound at 2-3 waves per SIMD there) for them.
 constexpr int move_shape_lds_bytes(int peak_kind, int noise_kind, int ppl, int threads) {
-    if (noise_kind == SMC_NOISE_HETERO) return 0;
+    (void)noise_kind;
     const int b = peak_kind == SMC_PEAK_GAUSS ? 4 : 8;
     const int limit = peak_kind == SMC_PEAK_XRD ? 40960 : 32768;
     return ppl * threads * b <= limit ? b : 0;
