@@ -77,7 +77,7 @@ XRD_LINEAR = (4, 1)
 # not, takes one issue slot of its SIMD; a stream of transcendentals alone runs at half rate
 # (a throughput probe on the MI355X), which binds only where they are more than half of the
 # instructions.  The move kernels' mixes are far below that, and their counters agree: the
-# bench move kernel issues VALU instructions at 0.91 of the peak counting each transcendental
+# bench move kernel issues VALU instructions at 0.93 of the peak counting each transcendental
 # once (at two slots each the count would exceed the peak).
 TRANS_COST = float(os.environ.get("SMC_TRANS_COST", "1.0"))
 # MI355X: 256 CUs x 4 SIMD x 16 lanes per clock x 2.4 GHz = 39.3e12 lane-instructions/s
