@@ -298,26 +298,6 @@ __global__ void __launch_bounds__(256) k_energy(const GroupDesc* __restrict__ gr
 // particle m * n + t (Sec. II.B.3).
 // LDS: the prior table [d]; per chain slot theta[d], increment s_j z_j [d], ln u_j [d];
 // then the per-component accept counters [d] and the cross-wave reduction buffer.
-// ---------------------------------------------------------------------------
-// Waves per SIMD the register allocator is asked to leave room for.  The cached
-// point state grows with PPL (x, D and the shapes: one for a Gaussian peak, two
-// for a pseudo-Voigt peak; y too and the deviance's temporaries for Poisson
-// counts); these limits are the largest that compile without spilling on gfx950
-// (pseudo-Voigt with Poisson counts at 32 points per lane spills a few words).  A chain
-// of several wavefronts (the cross-wave reduction) needs a few more registers: one wave
-// less where the limit is 4 or 5.
-constexpr int move_min_waves(int peak, int noise, int points, int wpc) {
-    int w;
-    if (noise == SMC_NOISE_GAUSS) {
-        if (peak == SMC_PEAK_GAUSS) w = points <= 16 ? 5 : (points <= 20 ? 4 : (points <= 24 ? 3 : 2));
-        else w = points <= 10 ? 5 : (points <= 16 ? 4 : (points <= 20 ? 3 : 2));
-    } else if (peak == SMC_PEAK_GAUSS) {
-        w = points <= 8 ? 5 : (points <= 14 ? 4 : (points <= 20 ? 3 : 2));
-    } else {
-        w = points <= 7 ? 5 : (points <= 12 ? 4 : (points <= 16 ? 3 : 2));
-    }
-    return wpc > 1 && w >= 4 ? w - 1 : w;
-}
 
 template <int PK, int NZ, int L, int WPC, int PPL>
 __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(const GroupDesc* __restrict__ groups,
@@ -343,7 +323,7 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(
     float* red = body + CPW * 3 * d + d;
     uint32_t* nevals = reinterpret_cast<uint32_t*>(red + 2 * WPC);   // [0] shape, [1] linear
     // the proposal's shapes, [chain slot][point][lane], 8-byte aligned after the above
-    constexpr int kSB = move_shape_lds_bytes(PK, NZ, PPL, 256);
+    constexpr int kSB = move_shape_lds_bytes(PK, NZ, PPL, LC);
     float* shp = lds + ((4 * d + CPW * 3 * d + d + 2 * WPC + 2 + 1) & ~1);
     float* my_shp = shp + (kSB / 4) * (slot * PPL * LC + lane);
 

@@ -263,7 +263,6 @@ __global__ void __launch_bounds__(256) k_energy_xps(const GroupDesc* __restrict_
     if (lane == 0) g.energy[i] = e;
 }
 
-constexpr int xps_min_waves(int points) { return points <= 5 ? 4 : (points <= 8 ? 3 : 2); }
 
 // MH move of a tempering stage (same stream layout, output slots and counters as k_move).
 template <int L, int PPL>
@@ -286,7 +285,7 @@ __global__ void __launch_bounds__(256, xps_min_waves(PPL)) k_move_xps(const Grou
     uint32_t* accc = reinterpret_cast<uint32_t*>(body + CPW * 3 * d);
     uint32_t* nevals = reinterpret_cast<uint32_t*>(body + CPW * 3 * d + d + 2);   // [0] shape, [1] linear
     // the proposal's shapes, [chain slot][point][lane] float2, 8-byte aligned after the above
-    constexpr int kSB = move_shape_lds_bytes(SMC_PEAK_PVOIGT, SMC_NOISE_HETERO, PPL, 256);
+    constexpr int kSB = move_shape_lds_bytes(SMC_PEAK_PVOIGT, SMC_NOISE_HETERO, PPL, L);
     float2* my_shp = reinterpret_cast<float2*>(lds + ((4 * d + CPW * 3 * d + d + 4 + 1) & ~1)) + (slot * PPL * L + lane);
 
     const bool active = slot < w.nchains;

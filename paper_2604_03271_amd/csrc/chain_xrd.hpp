@@ -283,7 +283,6 @@ __global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256) k_energy_xrd(con
     if (lane == 0) g.energy[i] = e;
 }
 
-constexpr int xrd_min_waves(int points) { return points <= 6 ? 4 : (points <= 14 ? 3 : 2); }
 
 template <int L, int WPC, int PPL>
 __global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256, xrd_min_waves(PPL))
@@ -309,7 +308,7 @@ __global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256, xrd_min_waves(PP
     float* red = body + CPW * 3 * d + d;
     uint32_t* nevals = reinterpret_cast<uint32_t*>(red + 2 * WPC);
     // the proposal's shapes, [chain slot][point][lane] float2, 8-byte aligned after the above
-    constexpr int kSB = move_shape_lds_bytes(SMC_PEAK_XRD, SMC_NOISE_POISSON, PPL, TPB);
+    constexpr int kSB = move_shape_lds_bytes(SMC_PEAK_XRD, SMC_NOISE_POISSON, PPL, LC);
     float2* my_shp = reinterpret_cast<float2*>(lds + ((4 * d + CPW * 3 * d + d + 2 * WPC + 2 + 1) & ~1)) +
                      (slot * PPL * LC + lane);
 

@@ -83,16 +83,44 @@ struct GroupDesc {
     const float* mu_ref;        // XRD peaks: reference positions [K]
 };
 
+// Waves per SIMD the register allocator is asked to leave room for.  The cached
+// point state grows with PPL (x, D and the shapes: one for a Gaussian peak, two
+// for a pseudo-Voigt peak; y too and the deviance's temporaries for Poisson
+// counts); these limits are the largest that compile without spilling on gfx950
+// (pseudo-Voigt with Poisson counts at 32 points per lane spills a few words).  A chain
+// of several wavefronts (the cross-wave reduction) needs a few more registers: one wave
+// less where the limit is 4 or 5.
+constexpr int move_min_waves(int peak, int noise, int points, int wpc) {
+    int w;
+    if (noise == SMC_NOISE_GAUSS) {
+        if (peak == SMC_PEAK_GAUSS) w = points <= 16 ? 5 : (points <= 20 ? 4 : (points <= 24 ? 3 : 2));
+        else w = points <= 10 ? 5 : (points <= 16 ? 4 : (points <= 20 ? 3 : 2));
+    } else if (peak == SMC_PEAK_GAUSS) {
+        w = points <= 8 ? 5 : (points <= 14 ? 4 : (points <= 20 ? 3 : 2));
+    } else {
+        w = points <= 7 ? 5 : (points <= 12 ? 4 : (points <= 16 ? 3 : 2));
+    }
+    return wpc > 1 && w >= 4 ? w - 1 : w;
+}
+
+// The XPS (Shirley) and XRD move kernels, by points per lane.
+constexpr int xps_min_waves(int points) { return points <= 5 ? 4 : (points <= 8 ? 3 : 2); }
+constexpr int xrd_min_waves(int points) { return points <= 6 ? 4 : (points <= 14 ? 3 : 2); }
+
 // Bytes of LDS per lane and point where a move kernel keeps the shapes of the current
 // proposal (an accepted shape proposal then copies them instead of evaluating them again):
-// 4 (one shape: Gaussian peak) or 8 (two: pseudo-Voigt, XRD), or 0 where a workgroup of
-// `threads` would need more than 32 KB (40 KB for the XRD kernels, whose occupancy is
-// register-bound at 2-3 waves per SIMD there) for them.
-constexpr int move_shape_lds_bytes(int peak_kind, int noise_kind, int ppl, int threads) {
-    (void)noise_kind;
+// 4 (one shape: Gaussian peak) or 8 (two: pseudo-Voigt, XRD), or 0 where the workgroups
+// that the kernel's register budget lets run on one CU would need more than 128 KB of the
+// CU's 160 KB for them (a 256-thread workgroup is one wave per SIMD; 512 threads two).
+constexpr int move_shape_lds_bytes(int peak_kind, int noise_kind, int ppl, int lanes) {
+    const int threads = lanes > 256 ? lanes : 256;
+    const int wpc = lanes > 64 ? lanes / 64 : 1;
+    const int waves = peak_kind == SMC_PEAK_XRD ? xrd_min_waves(ppl)
+                      : noise_kind == SMC_NOISE_HETERO ? xps_min_waves(ppl)
+                                                       : move_min_waves(peak_kind, noise_kind, ppl, wpc);
+    const int wgs = waves * 256 / threads > 1 ? waves * 256 / threads : 1;
     const int b = peak_kind == SMC_PEAK_GAUSS ? 4 : 8;
-    const int limit = peak_kind == SMC_PEAK_XRD ? 40960 : 32768;
-    return ppl * threads * b <= limit ? b : 0;
+    return wgs * threads * ppl * b <= 131072 ? b : 0;
 }
 
 // One workgroup of the move / energy kernels: chains [chain0, chain0 + nchains) of a group.

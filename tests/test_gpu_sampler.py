@@ -76,6 +76,7 @@ def _move_inputs(orc, spec, K, M, seed):
     ("config1", 2, 300, 3, True, 0.2, 16),
     ("config2", 5, 128, 4, True, 1e-3, 0),
     ("config2", 3, 96, 2, False, 0.05, 64),
+    ("config2", 4, 96, 2, True, 1e-3, 32),     # 32 points per lane (2 waves per SIMD)
     ("config3", 12, 64, 2, True, 1e-4, 256),
 ])
 def test_move_matches_reference(orc, cfg, K, M, n, wf, beta, lanes):
