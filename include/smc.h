@@ -91,12 +91,13 @@ typedef struct {
  * The XRD powder profile of App. E: peaks (A, shift, r, alpha, u, v, w, s, t) at reference
  * positions mu_ref (position = mu_ref + shift; Caglioti Gaussian width, sec/tan Lorentzian
  * width, asymmetry alpha above the position; x in degrees 2theta, 0 < x < 180) with the
- * pseudo-Voigt background (a, sigma_bg, r_bg, b) and Poisson counts, N <= 5120; XRD peaks and
+ * pseudo-Voigt background (a, sigma_bg, r_bg, b) and Poisson counts, N <= 10240; XRD peaks and
  * the XRD background go together.  A parameter vector whose squared Caglioti width is not
  * positive, or whose Lorentzian width is zero, has no defined model and gets energy +inf
  * (it is never accepted). */
 typedef struct {
-    int32_t n_points;            /* N >= 1 */
+    int32_t n_points;            /* N >= 1; at most 8192 for the Gaussian / pseudo-Voigt families
+                                    (256 lanes x 32 points), 1024 (XPS form), 10240 (XRD) */
     const double* x;             /* (host) [N]; copied at init and rounded to FP32 */
     const double* y;             /* (host) [N]; Poisson counts must be >= 0 */
     int32_t peak_kind;           /* SMC_PEAK_* */

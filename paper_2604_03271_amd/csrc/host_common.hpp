@@ -14,6 +14,7 @@ namespace smc {
 constexpr int kMaxK = 64;
 constexpr int kMaxXpsPoints = 1024;   // XPS model form: 64 lanes x 16 points
 constexpr int kMaxXrdPoints = 10240;  // XRD powder profile: 512 lanes x 20 points
+constexpr int kMaxPoints = 8192;      // Gaussian / pseudo-Voigt families: 256 lanes x 32 points
 
 struct Tile {
     int lc, pi, lanes, ppl;

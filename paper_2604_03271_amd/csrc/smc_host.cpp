@@ -81,6 +81,7 @@ smc_status validate(const smc_problem* p, const smc_options* o) {
             if (!(p->x[i] > 0.0 && p->x[i] < 180.0)) return SMC_EINVAL;
     }
     if (p->noise_kind < SMC_NOISE_GAUSS || p->noise_kind > SMC_NOISE_HETERO) return SMC_EINVAL;
+    if (p->peak_kind != SMC_PEAK_XRD && p->n_points > kMaxPoints) return SMC_EINVAL;
     if (p->noise_kind == SMC_NOISE_GAUSS && !(p->sigma > 0.0 && std::isfinite(p->sigma))) return SMC_EINVAL;
     if (xps_model(*p)) {
         // the XPS model form: pseudo-Voigt peaks, Shirley background, heteroscedastic noise

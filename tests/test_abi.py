@@ -198,3 +198,9 @@ def test_tuner_rejects_bad_arguments_before_the_device():
     assert L.smc_tune_lanes(pr.ref, ctypes.byref(o), 2, None, None) == native.SMC_EINVAL
     bad = native.options(n_particles=1)
     assert L.smc_tune_lanes(pr.ref, ctypes.byref(bad), 2, ctypes.byref(lanes), None) == native.SMC_EINVAL
+
+
+def test_point_limit_of_the_peak_families():
+    rng = np.random.default_rng(3)
+    assert _init_status(W.random_spectrum(rng, 8192, "pvoigt", "linear", "gauss", k_true=2)) != native.SMC_EINVAL
+    assert _init_status(W.random_spectrum(rng, 8193, "pvoigt", "linear", "gauss", k_true=2)) == native.SMC_EINVAL
