@@ -108,6 +108,11 @@ hipError_t upload_entry(const Entry& e, hipStream_t s, std::vector<std::vector<c
     err = hipMemcpyAsync(const_cast<float*>(e.groups[0].y), e.spec.yf.data(), sizeof(float) * e.spec.prob.n_points,
                          hipMemcpyHostToDevice, s);
     if (err != hipSuccess) return err;
+    if (!e.spec.mref_f.empty()) {   // XRD reference positions
+        err = hipMemcpyAsync(const_cast<float*>(e.groups[0].mu_ref), e.spec.mref_f.data(),
+                             sizeof(float) * e.spec.mref_f.size(), hipMemcpyHostToDevice, s);
+        if (err != hipSuccess) return err;
+    }
     std::vector<GroupState> zero(e.ng);
     keep.emplace_back(reinterpret_cast<const char*>(zero.data()),
                       reinterpret_cast<const char*>(zero.data()) + sizeof(GroupState) * e.ng);

@@ -143,3 +143,44 @@ def test_server_mixed_shapes_equal_alone():
     for i, (sp, kw) in enumerate(reqs):
         assert got[i]["status"] == 0
         assert np.array_equal(got[i]["logz"], _alone(sp, kw))
+
+
+def _family_mix():
+    """Spectra of every model family: Gaussian and pseudo-Voigt peaks, the XPS form (Shirley,
+    heteroscedastic noise) and the XRD profile (reference positions, Poisson counts)."""
+    specs, _ = _small_batch(n=2)
+    xps = W.xps_shirley(index=3, n=200, k_min=1, k_max=2)
+    xrd = W.xrd_powder(n=300, index=2, lo=20.0, hi=35.0, scale=0.01)
+    xrd.k_min, xrd.k_max = 2, 3
+    return specs + [xps, xrd]
+
+
+def test_batch_of_every_family_equals_alone():
+    torch_cuda()
+    specs = _family_mix()
+    kw = dict(n_particles=1024, n_moves=16, waste_free=True, seed=33)
+    say("batch families", [(sp.peak_kind, sp.n) for sp in specs])
+    got = native.smc_batch_run(specs, native.options(**kw))
+    for sp, lz in zip(specs, got):
+        ref = _alone(sp, kw)
+        assert np.array_equal(lz, ref), (sp.peak_kind, lz, ref)
+        assert np.all(np.isfinite(lz))
+
+
+def test_server_of_every_family_equals_alone():
+    torch_cuda()
+    specs = _family_mix()
+    kw = dict(n_particles=1024, n_moves=16, waste_free=True, seed=34)
+    say("server families")
+    srv = _server(1 << 30, kw)
+    probs = [native.Problem(sp) for sp in specs]
+    for i, pr in enumerate(probs):
+        assert native.lib().smc_server_submit(srv, pr.ref, None, 500 + i) == 0
+    res = _server_results(srv, len(specs))
+    native.lib().smc_server_destroy(srv)
+    assert len(res) == len(specs)
+    for i, sp in enumerate(specs):
+        st, lz, best, lat = res[500 + i]
+        assert st == 0
+        ref = _alone(sp, kw)
+        assert np.array_equal(np.asarray(lz), ref), (sp.peak_kind, lz, ref)
