@@ -46,7 +46,7 @@ sys.path.insert(0, ROOT)
 SHAPE_VALU = {"pvoigt": 7, "gauss": 5}
 SHAPE_TRANS = {"pvoigt": 2, "gauss": 1}
 LINEAR_VALU = 2
-# Poisson counts (config 3): the point term needs f (the fma that adds the term's value to the
+# Poisson counts (N=4096, 16 pseudo-Voigt peaks): the point term needs f (the fma that adds the term's value to the
 # rest of the model), ln f and y ln f subtracted and summed (fma, add): a shape proposal is the
 # profile's shape work (pseudo-Voigt 4 VALU + exp2, rcp; Gaussian 3 + exp2), 2 or 1 fma for the
 # value, then 2 VALU + log; a linear proposal 3 VALU + log.
@@ -162,10 +162,10 @@ def cpu_baseline(spec, K, seconds_target=10.0):
 
 
 def batched(native, workloads, n_spectra, P=8192, plain_sample=4):
-    """Config 4: n_spectra uneven spectra, every K = 1..8, in one pool (captured stage replayed).
+    """Uneven batch: n_spectra spectra of N~U{200..4000}, every K = 1..8, in one pool (captured stage replayed).
     The plain comparator runs a few of the same spectra one at a time, one K at a time."""
     import torch
-    specs = workloads.config4(n_spectra=n_spectra)
+    specs = workloads.uneven_batch(n_spectra=n_spectra)
     opt = native.options(n_particles=P, n_moves=16, waste_free=True, seed=3)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -181,7 +181,7 @@ def batched(native, workloads, n_spectra, P=8192, plain_sample=4):
         torch.cuda.synchronize()
         tp += time.perf_counter() - ts
         s.close()
-    return {"workload": f"config-4 batch: {n_spectra} spectra, N~U{{200..4000}}, Gaussian/pseudo-Voigt, "
+    return {"workload": f"uneven batch: {n_spectra} spectra, N~U{{200..4000}}, Gaussian/pseudo-Voigt, "
                         f"K=1..8, P={P}, waste-free n=16",
             "spectra_per_s": n_spectra / dt, "batch_s": dt,
             "plain_gpu_spectra_per_s": plain_sample / tp,
@@ -194,9 +194,9 @@ def progress(*a):
 
 
 def served(native, workloads, n_arrivals, rate, budget=64 << 30):
-    """Config 5: Poisson(rate) arrivals, 70% config-1-shaped and 30% config-2-shaped requests,
+    """Arrival stream: Poisson(rate) arrivals, 70% N=201 Gaussian-peak and 30% N=1001 pseudo-Voigt requests,
     submitted in real time to the continuous-batching server."""
-    trace = workloads.config5_trace(n_arrivals=n_arrivals, rate=rate)
+    trace = workloads.arrival_trace(n_arrivals=n_arrivals, rate=rate)
     o1 = native.options(n_particles=512, n_moves=10, waste_free=False, seed=5)
     o2 = native.options(n_particles=65536, n_moves=16, waste_free=True, seed=5)
     srv = native.Server(budget, o1)
@@ -218,8 +218,8 @@ def served(native, workloads, n_arrivals, rate, budget=64 << 30):
     dur = time.perf_counter() - t0
     srv.close()
     lat = np.array(lat)
-    return {"workload": f"config-5 stream: {n_arrivals} Poisson({rate}/s) arrivals, 70% config-1 shape "
-                        "(P=512, standard n=10), 30% config-2 shape (P=65536, waste-free n=16)",
+    return {"workload": f"arrival stream: {n_arrivals} Poisson({rate}/s) arrivals, 70% N=201 Gaussian-peak "
+                        "(P=512, standard n=10), 30% N=1001 pseudo-Voigt (P=65536, waste-free n=16)",
             "spectra_per_s": n_arrivals / dur, "duration_s": dur,
             "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
             "offered_per_s": rate}
@@ -228,7 +228,7 @@ def served(native, workloads, n_arrivals, rate, budget=64 << 30):
 def _workload(name, native_options, workloads, particles, lanes=0):
     """(spectrum, options, description) of a named workload."""
     if name == "xps-pv":
-        spec = workloads.config2(0)
+        spec = workloads.pvoigt5_n1001(0)
         P, n = particles or 65536, 16
         desc = (f"XPS-like spectrum N=1001, 5 pseudo-Voigt peaks + linear background, sigma=0.02, "
                 f"K=1..8, P={P} per K, waste-free n={n}")
@@ -237,16 +237,16 @@ def _workload(name, native_options, workloads, particles, lanes=0):
         P, n = particles or 2_000_000, 100
         desc = (f"XPS-like stand-in N={spec.n}, pseudo-Voigt peaks on a dynamic Shirley background, "
                 f"heteroscedastic noise, K={spec.k_min}..{spec.k_max}, P={P} per K, waste-free n={n}")
-    elif name == "config1":
-        spec = workloads.config1(0)
+    elif name == "gauss3-n201":
+        spec = workloads.gauss3_n201(0)
         P, n = particles or 512, 10
-        desc = f"config 1: N=201, 3 Gaussian peaks, sigma=0.05, K=1..4, P={P} per K, standard n={n}"
+        desc = f"N=201, 3 Gaussian peaks, sigma=0.05, K=1..4, P={P} per K, standard n={n}"
         return spec, native_options(n_particles=P, n_moves=n, waste_free=False, seed=0, profile=True,
                                     lanes_per_chain=lanes), desc
-    elif name == "config3":
-        spec = workloads.config3(0)
+    elif name == "pv16-poisson-n4096":
+        spec = workloads.pvoigt16_poisson_n4096(0)
         P, n = particles or 16384, 16
-        desc = (f"config 3: XRD-like N=4096, 16 pseudo-Voigt peaks + constant background, Poisson counts, "
+        desc = (f"XRD-like N=4096, 16 pseudo-Voigt peaks + constant background, Poisson counts, "
                 f"K=12..20, P={P} per K, waste-free n={n}")
     elif name.startswith("xrd-"):
         N = int(name.split("-")[1])
@@ -271,21 +271,21 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="xps-pv",
                     choices=["xps-pv", "paper-k3", "paper-k10", "paper-k30", "xps-shirley", "xrd-1000",
-                             "xrd-5000", "xrd-10000", "config1", "config3"])
+                             "xrd-5000", "xrd-10000", "gauss3-n201", "pv16-poisson-n4096"])
     ap.add_argument("--particles", type=int, default=0, help="particles per K (default: the workload's)")
     ap.add_argument("--lanes", type=int, default=0, help="lanes per chain (default: the library's tile rule)")
     ap.add_argument("--tune", action="store_true", help="lanes per chain from the library's autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--batch", type=int, default=0, help="also run the config-4 batch with this many spectra")
-    ap.add_argument("--serve", type=int, default=0, help="also serve this many config-5 arrivals")
+    ap.add_argument("--batch", type=int, default=0, help="also run the uneven batch with this many spectra")
+    ap.add_argument("--serve", type=int, default=0, help="also serve this many arrivals of the Poisson stream")
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--rates", default="", help="comma-separated arrival rates: serve --serve arrivals at each")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one device-to-device copy of this many bytes (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the sampler's groups are independent and this build "
+        print("bench.py runs on one GPU only: the sampler's groups are independent and the bench "
               "measures one GPU's share; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 

@@ -11,7 +11,7 @@ The recipes stand in for the paper's measured and artificial spectra, which
 are not available: XPS-like spectra (N ~ 300-1000, up to ~10 peaks, Sec. III.A.2
 and III.B.2) and XRD-like Poisson patterns (N 1000-10000, Sec. III.A.1 and
 App. C).  Every draw uses ``numpy.random.default_rng(seed)`` with the data seed
-1000 * config + spectrum index.
+1000 * (workload number) + spectrum index.
 """
 from __future__ import annotations
 
@@ -72,13 +72,13 @@ def _synth(x, kind, peaks, bg=(0.0, 0.0)):
     return f
 
 
-# --- the five workloads ------------------------------------------------------------------
+# --- synthetic spectra: the scaled workloads ------------------------------------------------------------------
 
 GAUSS_PRIORS: List[Prior] = [("gamma", 2.0, 1.0), ("uniform", 0.0, 10.0), ("gamma", 2.0, 0.25)]
 PV_PRIORS: List[Prior] = [("gamma", 2.0, 1.0), ("uniform", 0.0, 10.0), ("gamma", 2.0, 4.0), ("uniform", 0.0, 1.0)]
 
 
-def config1(index: int = 0) -> Spectrum:
+def gauss3_n201(index: int = 0) -> Spectrum:
     """XPS-like: N=201 on [0,10], 3 Gaussian peaks (A~U[0.5,2], mu~U[2,8], SD~U[0.2,0.8],
     precision b=1/SD^2), sigma=0.05, candidates K=1..4."""
     rng = np.random.default_rng(1000 * 1 + index)
@@ -93,7 +93,7 @@ def config1(index: int = 0) -> Spectrum:
                     truth={"K": 3, "peaks": peaks}, uid=1000 + index)
 
 
-def config2(index: int = 0) -> Spectrum:
+def pvoigt5_n1001(index: int = 0) -> Spectrum:
     """XPS-like at GPU scale: N=1001 on [0,10], 5 pseudo-Voigt peaks (A~U[0.5,2], mu~U[2,8],
     HWHM~U[0.2,0.8], eta~U[0,1]) on a linear background (c0~U[0,0.5], c1~U[-0.05,0.05]),
     sigma=0.02, candidates K=1..8."""
@@ -113,7 +113,7 @@ def config2(index: int = 0) -> Spectrum:
                     truth={"K": 5, "peaks": peaks, "bg": (c0, c1)}, uid=2000 + index)
 
 
-def config3(index: int = 0) -> Spectrum:
+def pvoigt16_poisson_n4096(index: int = 0) -> Spectrum:
     """XRD-like: N=4096 on 2theta in [10,90], 16 narrow pseudo-Voigt peaks (A~U[1e3,1e4],
     mu~U[12,88], HWHM~U[0.05,0.3], eta~U[0,1]) on a constant background b=100, Poisson
     counts, candidates K=12..20."""
@@ -134,9 +134,9 @@ def config3(index: int = 0) -> Spectrum:
                     truth={"K": 16, "peaks": peaks, "bg": (100.0,)}, uid=3000 + index)
 
 
-def config4(n_spectra: int = 512, index0: int = 0) -> List[Spectrum]:
+def uneven_batch(n_spectra: int = 512, index0: int = 0) -> List[Spectrum]:
     """Batch of independent spectra: N_s~U{200..4000} on [0,10], kind Gaussian or
-    pseudo-Voigt 50/50, K_true~U{1..6} with the config-1 / config-2 ranges, no background,
+    pseudo-Voigt 50/50, K_true~U{1..6} with the ranges of the N=201 and N=1001 spectra, no background,
     sigma_s~U[0.01,0.1], candidates K=1..8."""
     out = []
     for s_idx in range(index0, index0 + n_spectra):
@@ -162,15 +162,15 @@ def config4(n_spectra: int = 512, index0: int = 0) -> List[Spectrum]:
     return out
 
 
-def config5_trace(n_arrivals: int = 2000, rate: float = 200.0, seed: int = 5000):
-    """Poisson(rate) arrival times with a 70/30 mix of config-1 and config-2 shaped requests.
+def arrival_trace(n_arrivals: int = 2000, rate: float = 200.0, seed: int = 5000):
+    """Poisson(rate) arrival times with a 70/30 mix of N=201 Gaussian-peak and N=1001 pseudo-Voigt requests.
     Returns a list of (arrival_time_s, Spectrum)."""
     rng = np.random.default_rng(seed)
     t = np.cumsum(rng.exponential(1.0 / rate, n_arrivals))
     kinds = rng.uniform(size=n_arrivals) < 0.7
     out = []
     for i in range(n_arrivals):
-        sp = config1(10000 + i) if kinds[i] else config2(10000 + i)
+        sp = gauss3_n201(10000 + i) if kinds[i] else pvoigt5_n1001(10000 + i)
         sp.uid = 50000 + i
         out.append((float(t[i]), sp))
     return out
@@ -194,7 +194,7 @@ def linear_gaussian(n: int = 40, K: int = 2, sigma: float = 0.3, m0: float = 0.5
 
 
 def k1_problem(n: int = 15, sigma: float = 0.4, seed: int = 11) -> Spectrum:
-    """One Gaussian peak with the config-1 priors on a short noisy grid (broad posterior)."""
+    """One Gaussian peak with the priors of the N=201 Gaussian-peak spectrum on a short noisy grid (broad posterior)."""
     rng = np.random.default_rng(seed)
     x = f32(np.linspace(0.0, 10.0, n))
     y = f32(_synth(x, "gauss", [(1.5, 4.3, 0.8)]) + sigma * rng.standard_normal(n))

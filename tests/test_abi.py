@@ -39,14 +39,14 @@ def test_strerror_and_defaults():
 
 
 def test_dim_and_energy_constant():
-    sp = W.config2(0)
+    sp = W.pvoigt5_n1001(0)
     pr = native.Problem(sp)
     assert pr.dim(5) == 22
-    sp1 = W.config1(0)
+    sp1 = W.gauss3_n201(0)
     assert native.Problem(sp1).dim(3) == 9
     c = native.Problem(sp1).energy_constant()
     assert c == pytest.approx(0.5 * 201 * math.log(2 * math.pi * 0.05 ** 2), rel=1e-14)
-    sp3 = W.config3(0)
+    sp3 = W.pvoigt16_poisson_n4096(0)
     from scipy.special import gammaln
     y = sp3.y
     ref = np.sum(y - np.where(y > 0, y * np.log(np.where(y > 0, y, 1.0)), 0.0) + gammaln(y + 1))
@@ -80,7 +80,7 @@ def _init_status(spec, **kw):
     (lambda s: None, {"n_particles": 200_000_000}),   # 12 components x P beyond 32-bit offsets
 ])
 def test_invalid_problems_rejected_on_host(mutate, kw):
-    sp = W.config1(0)
+    sp = W.gauss3_n201(0)
     sp.x = sp.x.copy()
     sp.y = sp.y.copy()
     mutate(sp)
@@ -88,7 +88,7 @@ def test_invalid_problems_rejected_on_host(mutate, kw):
 
 
 def test_negative_poisson_counts_rejected():
-    sp = W.config3(0)
+    sp = W.pvoigt16_poisson_n4096(0)
     sp.y = sp.y.copy()
     sp.y[3] = -1.0
     assert _init_status(sp) == native.SMC_EINVAL
@@ -190,7 +190,7 @@ def test_xrd_point_limit_and_short_mu_ref():
 
 def test_tuner_rejects_bad_arguments_before_the_device():
     L = native.lib()
-    pr = native.Problem(W.config1(0))
+    pr = native.Problem(W.gauss3_n201(0))
     o = native.options()
     lanes = ctypes.c_int32()
     assert L.smc_tune_lanes(None, ctypes.byref(o), 2, ctypes.byref(lanes), None) == native.SMC_EINVAL

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _small_batch(n=6, P=1024):
-    specs = W.config4(n_spectra=n, index0=100)
+    specs = W.uneven_batch(n_spectra=n, index0=100)
     for sp in specs:
         sp.k_max = 3
     return specs, dict(n_particles=P, n_moves=16, waste_free=True, seed=21)
@@ -107,7 +107,7 @@ def test_server_admission_under_small_budget():
     try:
         for i, pr in enumerate(probs):
             assert native.lib().smc_server_submit(srv, pr.ref, None, i) == 0
-        big = native.Problem(W.config2(0))
+        big = native.Problem(W.pvoigt5_n1001(0))
         assert native.lib().smc_server_submit(srv, big.ref, None, 99) == native.SMC_EBUDGET
         res = _server_results(srv, len(probs))
     finally:
@@ -118,7 +118,7 @@ def test_server_admission_under_small_budget():
 
 
 def test_server_mixed_shapes_equal_alone():
-    """Config-1-shaped (standard, n=10) and config-2-shaped (waste-free, n=16) requests with
+    """N=201 Gaussian-peak (standard, n=10) and N=1001 pseudo-Voigt (waste-free, n=16) requests with
     their own options in one pool; every result equals the same request run alone."""
     torch_cuda()
     say("server mixed shapes")
@@ -126,9 +126,9 @@ def test_server_mixed_shapes_equal_alone():
     reqs = []
     for i in range(4):
         if i % 2 == 0:
-            sp, kw = W.config1(200 + i), dict(n_particles=512, n_moves=10, waste_free=False, seed=9)
+            sp, kw = W.gauss3_n201(200 + i), dict(n_particles=512, n_moves=10, waste_free=False, seed=9)
         else:
-            sp, kw = W.config2(200 + i), dict(n_particles=2048, n_moves=16, waste_free=True, seed=9)
+            sp, kw = W.pvoigt5_n1001(200 + i), dict(n_particles=2048, n_moves=16, waste_free=True, seed=9)
             sp.k_max = 4
         sp.uid = 700 + i
         reqs.append((sp, kw))

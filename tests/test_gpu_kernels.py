@@ -111,7 +111,7 @@ def test_energy_matches_reference(orc, peak, bg, noise, N, K, lanes):
     torch = torch_cuda()
     rng = np.random.default_rng(N * 31 + K)
     if noise == "poisson" and N == 4096:
-        spec = W.config3(0)
+        spec = W.pvoigt16_poisson_n4096(0)
     else:
         spec = W.random_spectrum(rng, N, peak, bg, noise, k_true=min(K, 4))
     n_theta = 301
@@ -132,7 +132,7 @@ def test_energy_matches_reference(orc, peak, bg, noise, N, K, lanes):
 def test_energy_every_tile_same_values(orc):
     """Every lane configuration evaluates the same energies (to rounding)."""
     torch = torch_cuda()
-    spec = W.config2(0)
+    spec = W.pvoigt5_n1001(0)
     rng = np.random.default_rng(5)
     th = _thetas(rng, spec, 5, 64)
     outs = []

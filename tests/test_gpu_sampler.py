@@ -31,7 +31,7 @@ def _gpu_init(spec, K, P, seed, lanes=0):
     return th.cpu().numpy()[:d * P].reshape(d, P).T.astype(np.float64), e.cpu().numpy().astype(np.float64)
 
 
-@pytest.mark.parametrize("cfg,K", [("config1", 3), ("config2", 5), ("config3", 12)])
+@pytest.mark.parametrize("cfg,K", [("gauss3_n201", 3), ("pvoigt5_n1001", 5), ("pvoigt16_poisson_n4096", 12)])
 def test_init_draws_follow_reference_streams(orc, cfg, K):
     spec = getattr(W, cfg)(0)
     P = 2048
@@ -54,7 +54,7 @@ def test_init_draws_follow_reference_streams(orc, cfg, K):
 
 
 def test_init_prior_laws():
-    spec = W.config1(0)
+    spec = W.gauss3_n201(0)
     say("init laws")
     th, _ = _gpu_init(spec, 2, 8192, seed=3)
     laws = [stats.gamma(2.0, scale=1.0), stats.uniform(0, 10), stats.gamma(2.0, scale=4.0)]
@@ -72,12 +72,12 @@ def _move_inputs(orc, spec, K, M, seed):
 
 
 @pytest.mark.parametrize("cfg,K,M,n,wf,beta,lanes", [
-    ("config1", 3, 256, 4, False, 0.01, 0),
-    ("config1", 2, 300, 3, True, 0.2, 16),
-    ("config2", 5, 128, 4, True, 1e-3, 0),
-    ("config2", 3, 96, 2, False, 0.05, 64),
-    ("config2", 4, 96, 2, True, 1e-3, 32),     # 32 points per lane (2 waves per SIMD)
-    ("config3", 12, 64, 2, True, 1e-4, 256),
+    ("gauss3_n201", 3, 256, 4, False, 0.01, 0),
+    ("gauss3_n201", 2, 300, 3, True, 0.2, 16),
+    ("pvoigt5_n1001", 5, 128, 4, True, 1e-3, 0),
+    ("pvoigt5_n1001", 3, 96, 2, False, 0.05, 64),
+    ("pvoigt5_n1001", 4, 96, 2, True, 1e-3, 32),     # 32 points per lane (2 waves per SIMD)
+    ("pvoigt16_poisson_n4096", 12, 64, 2, True, 1e-4, 256),
 ])
 def test_move_matches_reference(orc, cfg, K, M, n, wf, beta, lanes):
     torch = torch_cuda()
@@ -112,7 +112,7 @@ def test_move_keeps_prior_at_beta0():
     """At beta = 0 the move targets the prior: starting from exact prior draws the
     marginals stay the prior's."""
     torch = torch_cuda()
-    spec = W.config1(0)
+    spec = W.gauss3_n201(0)
     K, M = 2, 4096
     say("move beta0")
     th0, e0 = _gpu_init(spec, K, M, seed=5)
@@ -168,43 +168,43 @@ def test_k1_quadrature():
     assert abs(lz.mean() - exact) <= 3 * se + 0.03, (lz.mean(), exact, se)
 
 
-def test_config1_parity_with_reference(orc):
-    """Config-1 shape (N=201, K=1..4, standard mode, n=10), 10 seeds on both sides."""
-    spec = W.config1(0)
+def test_gauss3_n201_parity_with_reference(orc):
+    """Three Gaussian peaks (N=201, K=1..4, standard mode, n=10), 10 seeds on both sides."""
+    spec = W.gauss3_n201(0)
     P = 2048
     opr = orc.Problem(spec)
     g, o = [], []
     for seed in range(1, 11):
-        say("e2e config1 seed", seed)
+        say("e2e gauss3_n201 seed", seed)
         g.append(_gpu_logz(spec, seed, n_particles=P, n_moves=10, waste_free=False))
         o.append([orc.run(opr, K, P, 10, False, seed + 1000, spec.uid).log_evidence for K in range(1, 5)])
     d, se = _stat_parity(g, o)
-    say("config1 diff", d, "se", se, "gpu", np.mean(g, 0), "ref", np.mean(o, 0))
+    say("gauss3_n201 diff", d, "se", se, "gpu", np.mean(g, 0), "ref", np.mean(o, 0))
     assert np.all(np.abs(d) <= 3 * se + 1e-9) and np.all(np.abs(d) <= 0.05 + 3 * se), (d, se)
     assert np.argmax(np.mean(g, 0)) == np.argmax(np.mean(o, 0))
 
 
-def test_config2_parity_with_reference(orc):
-    """Config-2 shape (N=1001, pseudo-Voigt + linear background, waste-free n=16) at a reduced
-    P = 4096 and K = 4..5 (clearly separated evidences), 10 seeds on both sides.  (Config 3's
+def test_pvoigt5_n1001_parity_with_reference(orc):
+    """Five pseudo-Voigt peaks (N=1001, pseudo-Voigt + linear background, waste-free n=16) at a reduced
+    P = 4096 and K = 4..5 (clearly separated evidences), 10 seeds on both sides.  (The N=4096 Poisson pattern's
     reference run takes minutes per K even at P = 512; its stage is checked at full size.)"""
-    spec = W.config2(0)
+    spec = W.pvoigt5_n1001(0)
     spec.k_min, spec.k_max = 4, 5
     P = 4096
     opr = orc.Problem(spec)
     g, o = [], []
     for seed in range(1, 11):
-        say("e2e config2 seed", seed)
+        say("e2e pvoigt5_n1001 seed", seed)
         g.append(_gpu_logz(spec, seed, n_particles=P, n_moves=16, waste_free=True))
         o.append([orc.run(opr, K, P, 16, True, seed + 1000, spec.uid).log_evidence for K in (4, 5)])
     d, se = _stat_parity(g, o)
-    say("config2 diff", d, "se", se, "gpu", np.mean(g, 0), "ref", np.mean(o, 0))
+    say("pvoigt5_n1001 diff", d, "se", se, "gpu", np.mean(g, 0), "ref", np.mean(o, 0))
     assert np.all(np.abs(d) <= 3 * se + 1e-9) and np.all(np.abs(d) <= 0.05 + 3 * se), (d, se)
     assert np.argmax(np.mean(g, 0)) == np.argmax(np.mean(o, 0))
 
 
 def test_sampler_trace_invariants():
-    spec = W.config1(1)
+    spec = W.gauss3_n201(1)
     say("trace invariants")
     s = native.Sampler(spec, native.options(seed=3, n_particles=1024, n_moves=10, waste_free=False))
     s.run()
@@ -223,15 +223,15 @@ def test_sampler_trace_invariants():
 
 def test_plain_path_same_results():
     """The one-K-at-a-time comparator runs the same kernels: identical log Z."""
-    spec = W.config1(2)
+    spec = W.gauss3_n201(2)
     say("plain vs grouped")
     a = _gpu_logz(spec, 4, n_particles=1024, n_moves=10, waste_free=False)
     b = _gpu_logz(spec, 4, n_particles=1024, n_moves=10, waste_free=False, plain=True)
     assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("cfg,P,wf,n", [("config2", 65536, True, 16), ("config3", 16384, True, 16),
-                                        ("config1", 512, False, 10)])
+@pytest.mark.parametrize("cfg,P,wf,n", [("pvoigt5_n1001", 65536, True, 16), ("pvoigt16_poisson_n4096", 16384, True, 16),
+                                        ("gauss3_n201", 512, False, 10)])
 def test_stage_matches_reference_at_full_size(orc, cfg, P, wf, n):
     """The stage kernel (spread over several workgroups per K at these sizes) against the
     reference's FP64 bisection, ESS and log-sum-exp on the same stage-0 energies."""
@@ -256,7 +256,7 @@ def test_stage_matches_reference_at_full_size(orc, cfg, P, wf, n):
 def test_evaluation_kinds():
     """Evaluations split by kind add up; about half the pseudo-Voigt proposals are of linear
     coefficients (A, eta of each peak, both background coefficients)."""
-    spec = W.config2(0)
+    spec = W.pvoigt5_n1001(0)
     say("evaluation kinds")
     s = native.Sampler(spec, native.options(seed=3, n_particles=4096, n_moves=16, waste_free=True))
     s.run()
@@ -268,7 +268,7 @@ def test_evaluation_kinds():
     s.close()
 
 
-@pytest.mark.parametrize("make,allowed", [(lambda: W.config2(0), {16, 32, 64, 256}),
+@pytest.mark.parametrize("make,allowed", [(lambda: W.pvoigt5_n1001(0), {16, 32, 64, 256}),
                                           (lambda: W.xrd_powder(n=1000), {64, 256, 512})])
 def test_tuner_picks_a_supported_lane_count(make, allowed):
     """The autotuner returns a lane count that holds the problem, caches it, and a run with it

@@ -60,7 +60,7 @@ def test_relabelled_summaries(orc, K, np_, nbg, P):
 def test_sampler_summaries_and_posterior_k(orc):
     """After a run: the context's summaries equal the reference's on the particles it holds,
     and p(K|D) equals the reference's from the same log evidences."""
-    spec = W.config1(0)
+    spec = W.gauss3_n201(0)
     say("sampler summaries")
     s = native.Sampler(spec, native.options(seed=5, n_particles=2048, n_moves=10, waste_free=False))
     with pytest.raises(native.SMCError) as e:
@@ -89,7 +89,7 @@ def test_sampler_summaries_and_posterior_k(orc):
 
 def test_summary_at_full_size(orc):
     """The bench workload's population (P = 65536, K = 5 pseudo-Voigt + linear background)."""
-    spec = W.config2(0)
+    spec = W.pvoigt5_n1001(0)
     say("summary full size")
     s = native.Sampler(spec, native.options(seed=2, n_particles=65536, n_moves=16, waste_free=True))
     s.run()

@@ -142,7 +142,7 @@ def test_k1_evidence_against_quadrature(orc):
 def test_flat_likelihood_exact(orc):
     """All amplitudes fixed at 0: the likelihood does not depend on theta, the ladder is one
     stage and log Z = -(N/2) ln(2 pi s^2) - sum y^2 / (2 s^2) exactly."""
-    sp = W.config1(0)
+    sp = W.gauss3_n201(0)
     sp.peak_prior = [("fixed", 0.0, 0.0), ("uniform", 0.0, 10.0), ("gamma", 2.0, 0.25)]
     pr = orc.Problem(sp)
     r = orc.run(pr, 3, n_particles=256, n_moves=3, waste_free=False, seed=1)
@@ -152,7 +152,7 @@ def test_flat_likelihood_exact(orc):
 
 
 def test_poisson_all_fixed_exact(orc):
-    sp = W.config3(0)
+    sp = W.pvoigt16_poisson_n4096(0)
     t = sp.truth
     K = 4
     rows = [[("fixed", p[0], 0), ("fixed", p[1], 0), ("fixed", p[2], 0), ("fixed", p[3], 0)] for p in t["peaks"][:K]]
@@ -170,7 +170,7 @@ def test_poisson_all_fixed_exact(orc):
 def test_mh_leaves_prior_invariant_at_beta0(orc):
     """At beta = 0 the component-wise MH kernel targets the prior: after many sweeps started
     from exact prior draws the marginals are still the prior's."""
-    sp = W.config1(0)
+    sp = W.gauss3_n201(0)
     pr = orc.Problem(sp)
     K, P = 2, 3000
     th, E = orc.init(pr, K, P, seed=17)
@@ -185,6 +185,6 @@ def test_mh_leaves_prior_invariant_at_beta0(orc):
 
 
 def test_bad_options(orc):
-    sp = W.config1(0)
+    sp = W.gauss3_n201(0)
     pr = orc.Problem(sp)
     assert orc.run(pr, 1, n_particles=100, n_moves=16, waste_free=True, seed=1).status == -1
