@@ -7,6 +7,7 @@ import time
 import numpy as np
 import pytest
 
+import oracle_runs
 from gpu_util import say, torch_cuda
 from paper_2604_03271_amd import native, workloads as W
 
@@ -46,9 +47,7 @@ def test_batch_reference_statistics(orc):
     specs, kw = _small_batch(n=3, P=2048)
     say("batch vs reference")
     got = native.smc_batch_run(specs, native.options(**kw))
-    sp = specs[1]
-    opr = orc.Problem(sp)
-    ref = [orc.run(opr, K, 2048, 16, True, 5, sp.uid).log_evidence for K in range(1, 4)]
+    ref = oracle_runs.log_evidence(orc, "batch_member", say)[0]
     assert int(np.argmax(got[1])) == int(np.argmax(ref))
     assert np.max(np.abs(np.asarray(got[1]) - np.asarray(ref))) < 1.0
 

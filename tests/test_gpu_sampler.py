@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 from scipy import stats
 
+import oracle_runs
 from gpu_util import delta_ok, dev, energy_constant, f32, say, torch_cuda
 from paper_2604_03271_amd import native, workloads as W
 
@@ -172,12 +173,11 @@ def test_gauss3_n201_parity_with_reference(orc):
     """Three Gaussian peaks (N=201, K=1..4, standard mode, n=10), 10 seeds on both sides."""
     spec = W.gauss3_n201(0)
     P = 2048
-    opr = orc.Problem(spec)
-    g, o = [], []
+    g = []
     for seed in range(1, 11):
         say("e2e gauss3_n201 seed", seed)
         g.append(_gpu_logz(spec, seed, n_particles=P, n_moves=10, waste_free=False))
-        o.append([orc.run(opr, K, P, 10, False, seed + 1000, spec.uid).log_evidence for K in range(1, 5)])
+    o = oracle_runs.log_evidence(orc, "gauss3_n201", say)
     d, se = _stat_parity(g, o)
     say("gauss3_n201 diff", d, "se", se, "gpu", np.mean(g, 0), "ref", np.mean(o, 0))
     assert np.all(np.abs(d) <= 3 * se + 1e-9) and np.all(np.abs(d) <= 0.05 + 3 * se), (d, se)
@@ -191,12 +191,11 @@ def test_pvoigt5_n1001_parity_with_reference(orc):
     spec = W.pvoigt5_n1001(0)
     spec.k_min, spec.k_max = 4, 5
     P = 4096
-    opr = orc.Problem(spec)
-    g, o = [], []
+    g = []
     for seed in range(1, 11):
         say("e2e pvoigt5_n1001 seed", seed)
         g.append(_gpu_logz(spec, seed, n_particles=P, n_moves=16, waste_free=True))
-        o.append([orc.run(opr, K, P, 16, True, seed + 1000, spec.uid).log_evidence for K in (4, 5)])
+    o = oracle_runs.log_evidence(orc, "pvoigt5_n1001", say)
     d, se = _stat_parity(g, o)
     say("pvoigt5_n1001 diff", d, "se", se, "gpu", np.mean(g, 0), "ref", np.mean(o, 0))
     assert np.all(np.abs(d) <= 3 * se + 1e-9) and np.all(np.abs(d) <= 0.05 + 3 * se), (d, se)

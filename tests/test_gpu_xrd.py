@@ -8,6 +8,7 @@ import math
 import numpy as np
 import pytest
 
+import oracle_runs
 from gpu_util import delta_ok, dev, energy_constant, f32, say, torch_cuda
 from paper_2604_03271_amd import native, workloads as W
 from test_gpu_sampler import _gpu_init, _gpu_logz, _stat_parity
@@ -151,12 +152,11 @@ def test_log_evidence_parity_with_reference(orc):
     spec.k_min, spec.k_max = 1, 2
     spec.mu_ref = spec.mu_ref[:2]
     P = 512
-    opr = orc.Problem(spec)
-    g, o = [], []
+    g = []
     for seed in range(1, 11):
         say("xrd e2e seed", seed)
         g.append(_gpu_logz(spec, seed, n_particles=P, n_moves=8, waste_free=False))
-        o.append([orc.run(opr, K, P, 8, False, seed + 1000, spec.uid).log_evidence for K in (1, 2)])
+    o = oracle_runs.log_evidence(orc, "xrd_n60", say)
     d, se = _stat_parity(g, o)
     say("xrd diff", d, "se", se, "gpu", np.mean(g, 0), "ref", np.mean(o, 0))
     assert np.all(np.abs(d) <= 3 * se + 1e-9) and np.all(np.abs(d) <= 0.05 + 3 * se), (d, se)
