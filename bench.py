@@ -63,14 +63,17 @@ XPS_LINEAR = (8, 2)
 # XRD powder profile (Poisson counts), per point.  Every proposal forms the term's value
 # on the rest of the model (2 fma) and the Poisson term f - y ln f into the sum (fma, add
 # and log2): 4 VALU + 1 transcendental, all a linear proposal (A, r; a, r_bg, b) needs,
-# from the cached shapes.  A peak shape proposal (shift, alpha, u, v, w, s, t) first forms
-# x - mu and its square (2), the asymmetry select (2), the Caglioti polynomial (2), a^2 c
-# (2), 1 + tan^2 (1), t tan + s sec and the a factor (3), -4 d^2 / Sigma^2 (2), Omega^2,
-# 4 d^2 and 1 + 4 d^2 / Omega^2 (3): 17 VALU + sqrt, rcp, exp2, rcp, rcp.  The
-# background's width proposal forms 4 x^2 / sigma_bg^2 (3) and 1 + z (1), exp2 and rcp.
-# Every sweep proposes each component once, so of the 7 K + 1 shape proposals per sweep
-# one is the background's.
-XRD_PEAK_SHAPE = (21, 6)
+# from the cached shapes.  Sigma^2 and Omega^2 both scale with a^2, so a peak's widths
+# enter as factors at a = 1, W1 = 1 / (u tan^2 - v tan + w) and W2 = 1 / Omega0^2, that
+# only a proposal of their own parameters changes.  Every peak shape proposal (shift,
+# alpha, u, v, w, s, t) forms x - mu (2), d^2 (1), the asymmetry select of 4 / a^2 (2),
+# z = 4 d^2 / a^2 (1), -z W1 (1) and 1 + z W2 (1): 8 VALU + exp2, rcp; a proposal of u, v or
+# w also forms W1 (2 fma + rcp), one of s or t W2 (1 + tan^2, t tan + s sec, Omega0^2: 4
+# VALU + sqrt, rcp).  Averaged over the seven kinds, each proposed once a sweep: 10 VALU +
+# 3 transcendental, plus the 4 + 1 above.  The background's width proposal forms
+# 4 x^2 / sigma_bg^2 (3) and 1 + z (1), exp2 and rcp.  Of the 7 K + 1 shape proposals per
+# sweep one is the background's.
+XRD_PEAK_SHAPE = (14, 4)
 XRD_BG_SHAPE = (8, 3)
 XRD_LINEAR = (4, 1)
 # Issue slots of one transcendental instruction.  Every VALU instruction, transcendental or

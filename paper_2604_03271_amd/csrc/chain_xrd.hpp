@@ -13,8 +13,12 @@
 // (sec(x/2) = sqrt(1 + tan^2(x/2)) for 0 < x < 180 degrees, formed when needed).
 // The current term's shapes G, L are cached: a proposal of A or r (or of the
 // background's a, r_bg, b) only forms the deviance from them; a proposal of a shift,
-// asymmetry or width parameter (or sigma_bg) re-evaluates them.  Where a Caglioti
-// argument is not positive the width is undefined and the energy is +inf.
+// asymmetry or width parameter (or sigma_bg) re-evaluates them.  So are the current
+// peak's width factors at a = 1, W1 = 1 / (u tan^2 - v tan + w) and
+// W2 = 1 / (s sec + t tan)^2: since Sigma^2 and Omega^2 both scale with a^2, a shift or
+// asymmetry proposal forms G and L from them and 4 (x - mu)^2 / a^2 alone, a proposal of
+// u, v or w forms W1 anew and one of s or t forms W2 anew.  Where a Caglioti argument is
+// not positive the width is undefined and the energy is +inf.
 #pragma once
 
 #include "chain.hpp"
@@ -22,16 +26,24 @@
 namespace smc {
 
 struct XrdC {
-    float mref, shift, alpha, u, v, w, s, t;  // shape (peak); bg: s = 1 / sigma_bg^2
-    float aG, aL, c0;                // value = aG G + aL L + c0
+    float mref, shift, ia4, u, v, w, s, t;  // shape (peak; ia4 = 4 / alpha^2); bg: s = 1 / sigma_bg^2
+    float aG, aL, c0;                        // value = aG G + aL L + c0
 };
+
+// What a proposal of component q of a peak re-evaluates: nothing (A, r: linear), the shapes
+// from the cached width factors (shift, alpha), W1 and the shapes (u, v, w) or W2 and the
+// shapes (s, t).
+enum XrdMode : int { kXrdLinear = 0, kXrdCachedW = 1, kXrdNewW1 = 2, kXrdNewW2 = 3 };
+__device__ __forceinline__ int xrd_peak_mode(int q) {
+    return (q == 0 || q == 2) ? kXrdLinear : (q == 1 || q == 3) ? kXrdCachedW : q <= 6 ? kXrdNewW1 : kXrdNewW2;
+}
 
 // Constants of peak k (th: its nine parameters) at reference position mref.
 __device__ __forceinline__ XrdC xrd_peak_consts(const float* th, float mref) {
     XrdC q;
     q.mref = mref;
     q.shift = th[1];
-    q.alpha = th[3];
+    q.ia4 = 4.0f * __builtin_amdgcn_rcpf(th[3] * th[3]);
     q.u = th[4];
     q.v = th[5];
     q.w = th[6];
@@ -59,9 +71,14 @@ template <int L, int WPC, int PPL>
 struct XrdChain {
     static constexpr int LC = L * WPC;
     static constexpr int TPB = LC > 256 ? LC : 256;   // threads per workgroup
+    // Width factors cached in registers up to 10 points per lane; beyond that they would
+    // spill, and every shape proposal evaluates both widths.
+    static constexpr bool kCW = PPL <= 10;
     float x[PPL], tn[PPL], y[PPL];
     float D[PPL];
     float S1[PPL], S2[PPL];
+    float W1[PPL], W2[PPL];   // width factors of the current term when it is a peak (kCW)
+    bool wbad = false;        // some Caglioti argument of the current peak is not positive
 
     __device__ __forceinline__ void load_points(const GroupDesc& g, int lane) {
         constexpr float kHalfRad = 3.14159265358979f / 360.0f;
@@ -75,26 +92,41 @@ struct XrdChain {
         }
     }
 
-    // Shapes of a peak at point p; `bad` collects undefined widths.
-    __device__ __forceinline__ void peak_shape(const XrdC& q, int p, float& e, float& l, bool& bad) const {
-        // x - mu as (x - mu_ref) - shift: x - mu_ref is exact near the peak (both FP32,
-        // within a factor of 2), so d carries no rounding of mu_ref + shift, which at
-        // 2theta ~ 30 is ~1e-6 degrees, enough to move the energy of a narrow peak by
-        // more than 1e-5 relative
-        const float d = (x[p] - q.mref) - q.shift;
-        const float d2 = d * d;
-        const float a = d >= 0.0f ? q.alpha : 1.0f;
+    // Width factors of a peak at point p (a = 1): W1 = 1 / Caglioti argument (`bad` collects
+    // the points where that argument is not positive) and W2 = 1 / Omega0^2.
+    __device__ __forceinline__ float peak_w1(const XrdC& q, int p, bool& bad) const {
         const float c = __builtin_fmaf(__builtin_fmaf(q.u, tn[p], -q.v), tn[p], q.w);
         bad |= !(c > 0.0f);
-        const float sig2 = a * a * c;
+        return __builtin_amdgcn_rcpf(c);
+    }
+
+    __device__ __forceinline__ float peak_w2(const XrdC& q, int p) const {
         // sec(x/2) from an opaque copy of tan(x/2): hoisted out of the sweep loop it would
         // cost PPL more live registers
         float tv = tn[p];
         asm volatile("" : "+v"(tv));
         const float sec = __builtin_sqrtf(__builtin_fmaf(tv, tv, 1.0f));
-        const float om = a * __builtin_fmaf(q.s, sec, q.t * tn[p]);
-        e = __builtin_amdgcn_exp2f(-4.0f * d2 * __builtin_amdgcn_rcpf(sig2));
-        l = __builtin_amdgcn_rcpf(__builtin_fmaf(4.0f * d2, __builtin_amdgcn_rcpf(om * om), 1.0f));
+        const float om = __builtin_fmaf(q.s, sec, q.t * tn[p]);
+        return __builtin_amdgcn_rcpf(om * om);
+    }
+
+    // Shapes of a peak at point p from its width factors: with z = 4 (x - mu)^2 / a^2,
+    // G = 2^(-z W1) (= exp(-4 ln2 (x - mu)^2 / Sigma^2)) and L = 1 / (1 + z W2).
+    __device__ __forceinline__ void peak_shape_w(const XrdC& q, int p, float w1, float w2, float& e,
+                                                 float& l) const {
+        // x - mu as (x - mu_ref) - shift: x - mu_ref is exact near the peak (both FP32,
+        // within a factor of 2), so d carries no rounding of mu_ref + shift, which at
+        // 2theta ~ 30 is ~1e-6 degrees, enough to move the energy of a narrow peak by
+        // more than 1e-5 relative
+        const float d = (x[p] - q.mref) - q.shift;
+        const float z = d * d * (d >= 0.0f ? q.ia4 : 4.0f);
+        e = __builtin_amdgcn_exp2f(-z * w1);
+        l = __builtin_amdgcn_rcpf(__builtin_fmaf(z, w2, 1.0f));
+    }
+
+    // Shapes of a peak at point p, widths evaluated; `bad` collects undefined widths.
+    __device__ __forceinline__ void peak_shape(const XrdC& q, int p, float& e, float& l, bool& bad) const {
+        peak_shape_w(q, p, peak_w1(q, p, bad), peak_w2(q, p), e, l);
     }
 
     __device__ __forceinline__ void bg_shape(const XrdC& q, int p, float& e, float& l) const {
@@ -134,41 +166,44 @@ struct XrdChain {
         return is_bg ? partial_cached_t<true>(q) : partial_cached_t<false>(q);
     }
 
-    template <bool BG>
-    __device__ __forceinline__ float partial_shape_t(const XrdC& q) const {
+    // A proposal's shapes at point p: the background's evaluated; a peak's from its width
+    // factors, cached or (the one the proposal changes) formed anew.
+    template <bool BG, int MODE>
+    __device__ __forceinline__ void prop_shape(const XrdC& q, int p, float& e, float& l, bool& bad) const {
+        if constexpr (BG) {
+            bg_shape(q, p, e, l);
+        } else if constexpr (!kCW) {
+            peak_shape(q, p, e, l, bad);
+        } else {
+            const float w1 = MODE == kXrdNewW1 ? peak_w1(q, p, bad) : W1[p];
+            const float w2 = MODE == kXrdNewW2 ? peak_w2(q, p) : W2[p];
+            peak_shape_w(q, p, w1, w2, e, l);
+        }
+    }
+
+    // The lane's share of a shape proposal's energy; with STORE, the proposal's shapes are
+    // left at sl[p * LC] (float2 units: this lane's entries of its chain's LDS area) for an
+    // accept.  A proposal that keeps the Caglioti argument inherits its validity.
+    template <bool BG, int MODE, bool STORE>
+    __device__ __forceinline__ float partial_shape_t(const XrdC& q, float2* sl) const {
         float acc = 0.0f;
-        bool bad = false;
+        bool bad = !BG && kCW && MODE != kXrdNewW1 && wbad;
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
             float e, l;
-            shape(BG, q, p, e, l, bad);
+            prop_shape<BG, MODE>(q, p, e, l, bad);
+            if constexpr (STORE) sl[p * LC] = make_float2(e, l);
             acc += poisson_dev(y[p], model<BG>(D[p], q, e, l));
         }
         return bad ? __builtin_inff() : acc;
     }
 
-    __device__ __forceinline__ float partial_shape(bool is_bg, const XrdC& q) const {
-        return is_bg ? partial_shape_t<true>(q) : partial_shape_t<false>(q);
-    }
-
-    // The same, leaving the proposal's shapes at sl[p * LC] (float2 units: this lane's
-    // entries of its chain's LDS area) for an accept.
-    template <bool BG>
-    __device__ __forceinline__ float partial_shape_store_t(const XrdC& q, float2* sl) const {
-        float acc = 0.0f;
-        bool bad = false;
-#pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-            float e, l;
-            shape(BG, q, p, e, l, bad);
-            sl[p * LC] = make_float2(e, l);
-            acc += poisson_dev(y[p], model<BG>(D[p], q, e, l));
-        }
-        return bad ? __builtin_inff() : acc;
-    }
-
-    __device__ __forceinline__ float partial_shape_store(bool is_bg, const XrdC& q, float2* sl) const {
-        return is_bg ? partial_shape_store_t<true>(q, sl) : partial_shape_store_t<false>(q, sl);
+    template <bool STORE>
+    __device__ __forceinline__ float partial_shape(bool is_bg, int mode, const XrdC& q, float2* sl) const {
+        if (is_bg) return partial_shape_t<true, kXrdCachedW, STORE>(q, sl);
+        if (mode == kXrdCachedW) return partial_shape_t<false, kXrdCachedW, STORE>(q, sl);
+        if (mode == kXrdNewW1) return partial_shape_t<false, kXrdNewW1, STORE>(q, sl);
+        return partial_shape_t<false, kXrdNewW2, STORE>(q, sl);
     }
 
     __device__ __forceinline__ void load_shapes(const float2* sl) {
@@ -180,10 +215,45 @@ struct XrdChain {
         }
     }
 
+    // The current term's shapes (and, for a peak, its width factors) from its constants.
     __device__ __forceinline__ void set_shapes(bool is_bg, const XrdC& q) {
+        if (is_bg) {
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) bg_shape(q, p, S1[p], S2[p]);
+            return;
+        }
         bool bad = false;
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) shape(is_bg, q, p, S1[p], S2[p], bad);
+        for (int p = 0; p < PPL; ++p) {
+            const float w1 = peak_w1(q, p, bad), w2 = peak_w2(q, p);
+            if constexpr (kCW) {
+                W1[p] = w1;
+                W2[p] = w2;
+            }
+            peak_shape_w(q, p, w1, w2, S1[p], S2[p]);
+        }
+        wbad = bad;
+    }
+
+    // An accepted shape proposal becomes current: its shapes (from LDS when STORED) and the
+    // width factor it changed.
+    template <bool STORED>
+    __device__ __forceinline__ void accept_shape(bool is_bg, int mode, const XrdC& q, const float2* sl) {
+        if constexpr (!STORED) {
+            set_shapes(is_bg, q);
+            return;
+        }
+        load_shapes(sl);
+        if (is_bg || !kCW) return;
+        if (mode == kXrdNewW1) {
+            bool bad = false;
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) W1[p] = peak_w1(q, p, bad);
+            wbad = bad;
+        } else if (mode == kXrdNewW2) {
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) W2[p] = peak_w2(q, p);
+        }
     }
 
     // Term k joins the fixed part of the model in D (from its cached shapes, or evaluated).
@@ -240,13 +310,11 @@ struct XrdChain {
         bool bad = false;
         for (int k = g.K; k >= 1; --k) bad |= include_eval(k == g.K, term_consts(g, th, k));
         const XrdC q0 = term_consts(g, th, 0);
+        set_shapes(false, q0);
         float acc = 0.0f;
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-            peak_shape(q0, p, S1[p], S2[p], bad);
-            acc += poisson_dev(y[p], model<false>(D[p], q0, S1[p], S2[p]));
-        }
-        return bad ? __builtin_inff() : acc;
+        for (int p = 0; p < PPL; ++p) acc += poisson_dev(y[p], model<false>(D[p], q0, S1[p], S2[p]));
+        return (bad || wbad) ? __builtin_inff() : acc;
     }
 
     __device__ __forceinline__ void transition(const GroupDesc& g, const float* th, int from, int to) {
@@ -362,20 +430,17 @@ __global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256, xrd_min_waves(PP
                     if (!prior_in_support(pr, vn)) continue;
                     const XrdC qn = CS::term_consts_with(g, th, k, q, vn);
                     const bool linear = xrd_linear(is_bg, q);
+                    const int mode = is_bg ? kXrdCachedW : xrd_peak_mode(q);
                     float part;
                     if (linear) part = cs.partial_cached(is_bg, qn);
-                    else if constexpr (kSB > 0) part = cs.partial_shape_store(is_bg, qn, my_shp);
-                    else part = cs.partial_shape(is_bg, qn);
+                    else part = cs.template partial_shape<(kSB > 0)>(is_bg, mode, qn, my_shp);
                     if (linear) ++my_linear;
                     else ++my_shape;
                     const float En = chain_sum<L, WPC>(part, red, parity);
                     const float log_alpha = -beta * (En - E) + prior_log_ratio(pr, vn, vo);
                     if (lnu[j] < log_alpha) {
                         E = En;
-                        if (!linear) {
-                            if constexpr (kSB > 0) cs.load_shapes(my_shp);
-                            else cs.set_shapes(is_bg, qn);
-                        }
+                        if (!linear) cs.template accept_shape<(kSB > 0)>(is_bg, mode, qn, my_shp);
                         th[j] = vn;
                         if (lane == 0) atomicAdd(&accc[j], 1u);
                     }
