@@ -204,3 +204,14 @@ def test_point_limit_of_the_peak_families():
     rng = np.random.default_rng(3)
     assert _init_status(W.random_spectrum(rng, 8192, "pvoigt", "linear", "gauss", k_true=2)) != native.SMC_EINVAL
     assert _init_status(W.random_spectrum(rng, 8193, "pvoigt", "linear", "gauss", k_true=2)) == native.SMC_EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU's share: --gpus above 1 exits with a message, before any
+    GPU work."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
