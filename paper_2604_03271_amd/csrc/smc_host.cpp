@@ -272,6 +272,9 @@ using namespace smc;
 
 // ------------------------------------------------------------------ context
 
+// Stages that smc_run puts into the stream between two reads of the group states.
+constexpr int kStagesPerRead = 4;
+
 struct smc_ctx {
     Spectrum spec;                   // owned copy of the problem
     smc_options opt{};
@@ -293,9 +296,11 @@ struct smc_ctx {
     double econst = 0.0;
     bool finished = false;
     uint64_t stage0_evals = 0;
-    // optional HIP-event timing of the launches
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    bool ev_move = false, ev_stage = false;
+    // optional HIP-event timing of the launches: one (start, end) pair per move launch
+    // (ev[2b], ev[2b + 1]) and per stage launch (ev[2 kStagesPerRead + 2b], ...) between
+    // two reads of the group states
+    hipEvent_t ev[4 * kStagesPerRead] = {};
+    int n_ev_move = 0, n_ev_stage = 0;
     double move_ms = 0.0, stage_ms = 0.0;
     int64_t move_launches = 0, stage_launches = 0;
 };
@@ -665,54 +670,72 @@ extern "C" smc_status smc_profile(const smc_ctx* c, double* out) {
     return SMC_OK;
 }
 
-static void collect_events(smc_ctx* c);
+static void collect_events(smc_ctx* c, int moves, int stages);
 
-static smc_status read_states(smc_ctx* c) {
+static int max_stage(const smc_ctx* c) {
+    int m = 0;
+    for (const GroupState& s : c->states) m = std::max(m, static_cast<int>(s.stage));
+    return m;
+}
+
+// Read the group states back.  With profiling, the timed launches since the last read are
+// collected: all of them when `before` < 0, else only the launches in which some group had
+// work, as many as the largest stage count advanced from `before` (a move launch did work
+// iff some group advanced a stage before it).
+static smc_status read_states(smc_ctx* c, int before = -1) {
     if (hipMemcpyAsync(c->states.data(), c->d_states, sizeof(GroupState) * c->ng, hipMemcpyDeviceToHost, c->stream) !=
         hipSuccess)
         return SMC_EDEVICE;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return SMC_EDEVICE;
-    if (c->opt.profile) collect_events(c);
+    if (c->opt.profile) {
+        const int real = before < 0 ? kStagesPerRead : std::max(0, max_stage(c) - before);
+        collect_events(c, std::min(real, c->n_ev_move), std::min(real, c->n_ev_stage));
+    }
     return SMC_OK;
 }
 
 // Launch wrappers that bracket the launch with HIP events when profiling.
 static hipError_t timed_stage(smc_ctx* c, const GroupDesc* groups, int n) {
-    const bool prof = c->opt.profile && !c->ev_stage;
-    if (prof && hipEventRecord(c->ev[2], c->stream) != hipSuccess) return hipErrorUnknown;
+    const bool prof = c->opt.profile && c->n_ev_stage < kStagesPerRead;
+    hipEvent_t* ev = c->ev + 2 * kStagesPerRead + 2 * c->n_ev_stage;
+    if (prof && hipEventRecord(ev[0], c->stream) != hipSuccess) return hipErrorUnknown;
     int dmax = 1;
     for (const GroupDesc& g : c->groups) dmax = std::max(dmax, g.d);
     const int P = c->opt.n_particles, M = c->opt.waste_free ? P / c->opt.n_moves : P;
     hipError_t e = launch_stage(StageLaunch{groups, n, P, M, dmax}, c->stream);
     if (prof && e == hipSuccess) {
-        e = hipEventRecord(c->ev[3], c->stream);
-        c->ev_stage = true;
+        e = hipEventRecord(ev[1], c->stream);
+        ++c->n_ev_stage;
     }
     return e;
 }
 
 static hipError_t timed_move(smc_ctx* c, const void* fn, int n_work, const MoveWork* work) {
-    const bool prof = c->opt.profile && !c->ev_move;
-    if (prof && hipEventRecord(c->ev[0], c->stream) != hipSuccess) return hipErrorUnknown;
+    const bool prof = c->opt.profile && c->n_ev_move < kStagesPerRead;
+    hipEvent_t* ev = c->ev + 2 * c->n_ev_move;
+    if (prof && hipEventRecord(ev[0], c->stream) != hipSuccess) return hipErrorUnknown;
     hipError_t e = launch_tiled(fn, c->tile, n_work, c->lds_move, c->d_groups, work, c->stream);
     if (prof && e == hipSuccess) {
-        e = hipEventRecord(c->ev[1], c->stream);
-        c->ev_move = true;
+        e = hipEventRecord(ev[1], c->stream);
+        ++c->n_ev_move;
     }
     return e;
 }
 
-static void collect_events(smc_ctx* c) {
+static void collect_events(smc_ctx* c, int moves, int stages) {
     float ms = 0.0f;
-    if (c->ev_move && hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) {
-        c->move_ms += ms;
-        ++c->move_launches;
-    }
-    if (c->ev_stage && hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) {
-        c->stage_ms += ms;
-        ++c->stage_launches;
-    }
-    c->ev_move = c->ev_stage = false;
+    for (int b = 0; b < moves; ++b)
+        if (hipEventElapsedTime(&ms, c->ev[2 * b], c->ev[2 * b + 1]) == hipSuccess) {
+            c->move_ms += ms;
+            ++c->move_launches;
+        }
+    const hipEvent_t* es = c->ev + 2 * kStagesPerRead;
+    for (int b = 0; b < stages; ++b)
+        if (hipEventElapsedTime(&ms, es[2 * b], es[2 * b + 1]) == hipSuccess) {
+            c->stage_ms += ms;
+            ++c->stage_launches;
+        }
+    c->n_ev_move = c->n_ev_stage = 0;
 }
 
 static const void* move_fn(const smc_ctx* c) {
@@ -770,12 +793,44 @@ extern "C" smc_status smc_step(smc_ctx* c, int32_t* all_done) {
     return SMC_OK;
 }
 
+// The whole run: kStagesPerRead stages (stage pipeline + move) go into the stream before
+// each read of the group states, so the host's round trip and launch work overlap the
+// device's.  A stage launched after a group has finished does nothing for it (every
+// stage and move kernel returns at once for a done group), so the states are those of
+// one stage per read.
 extern "C" smc_status smc_run(smc_ctx* c) {
     if (!c) return SMC_EINVAL;
-    int32_t done = 0;
-    while (!done) {
-        smc_status st = smc_step(c, &done);
+    if (c->opt.plain) {
+        int32_t done = 0;
+        while (!done) {
+            smc_status st = smc_step(c, &done);
+            if (st != SMC_OK) return st;
+        }
+        return SMC_OK;
+    }
+    while (!c->finished) {
+        const int before = max_stage(c);
+        for (int b = 0; b < kStagesPerRead; ++b) {
+            if (timed_stage(c, c->d_groups, c->ng) != hipSuccess) return SMC_EDEVICE;
+            if (timed_move(c, move_fn(c), c->n_work, c->d_work) != hipSuccess) return SMC_EDEVICE;
+        }
+        smc_status st = read_states(c, before);
         if (st != SMC_OK) return st;
+        bool done = true, marked = true;
+        for (const GroupState& s : c->states) {
+            if (s.status != SMC_OK) return s.status;
+            done = done && (s.done || s.beta >= 1.0);
+            marked = marked && s.done;
+        }
+        if (done) {
+            if (!marked) {
+                // one more stage launch records the final acceptance and marks the groups done
+                if (timed_stage(c, c->d_groups, c->ng) != hipSuccess) return SMC_EDEVICE;
+                st = read_states(c);
+                if (st != SMC_OK) return st;
+            }
+            c->finished = true;
+        }
     }
     return SMC_OK;
 }

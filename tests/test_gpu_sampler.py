@@ -229,6 +229,33 @@ def test_plain_path_same_results():
     assert np.array_equal(a, b)
 
 
+def test_run_equals_stepping():
+    """smc_run puts several stages into the stream per read of the states; stages launched
+    after a group has finished do nothing, so the results equal one stage per smc_step
+    call bit for bit, and the profiled move launches are the stages that did work."""
+    spec = W.gauss3_n201(3)
+    say("run vs step")
+    for wf, n in ((False, 10), (True, 8)):
+        kw = dict(seed=6, n_particles=1024, n_moves=n, waste_free=wf, profile=True)
+        a = native.Sampler(spec, native.options(**kw)).run()
+        b = native.Sampler(spec, native.options(**kw))
+        while not b.step():
+            pass
+        assert np.array_equal(a.log_evidence(), b.log_evidence())
+        stages = max(a.stage_info(K)[0] for K in range(1, 5))
+        for K in range(1, 5):
+            ta, tb = a.trace(K), b.trace(K)
+            for key in ta:
+                assert np.array_equal(ta[key], tb[key]), key
+            assert a.stage_info(K) == b.stage_info(K)
+            ta_, tb_ = a.particles(K), b.particles(K)
+            assert np.array_equal(ta_[0], tb_[0]) and np.array_equal(ta_[1], tb_[1])
+        pa, pb = a.profile(), b.profile()
+        assert pa["move_launches"] == stages == pb["move_launches"], (pa, pb, stages)
+        a.close()
+        b.close()
+
+
 @pytest.mark.parametrize("cfg,P,wf,n", [("pvoigt5_n1001", 65536, True, 16), ("pvoigt16_poisson_n4096", 16384, True, 16),
                                         ("gauss3_n201", 512, False, 10)])
 def test_stage_matches_reference_at_full_size(orc, cfg, P, wf, n):
