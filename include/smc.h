@@ -144,7 +144,12 @@ smc_status smc_init(smc_ctx** out, const smc_problem* prob, const smc_options* o
  * move at beta = 1. */
 smc_status smc_step(smc_ctx* ctx, int32_t* all_done);
 
-/* smc_step until every K has reached beta = 1 (including its final move). */
+/* Every stage until every K has reached beta = 1 (including its final move): the same
+ * states, traces and log Z as calling smc_step until it reports all_done, bit for bit.  Four
+ * stages go into the stream per read of the small per-K state (a stage launched after a K
+ * has finished does nothing for it), so the host's round trip overlaps device work.  With
+ * opt.profile the timed move launches are those in which some K still had work.  Errors as
+ * smc_step (the first K whose status is not SMC_OK). */
 smc_status smc_run(smc_ctx* ctx);
 
 /* Start again from stage 0 on the resident data with a new seed (no allocation, no copy of
