@@ -409,8 +409,7 @@ __device__ inline void chunk_range(const GroupDesc& g, int c, int& i0, int& i1) 
     i1 = min(g.P, i0 + kStageChunk);
 }
 
-__global__ void __launch_bounds__(kChunkThreads) k_st_stats(const GroupDesc* __restrict__ groups, int maxch) {
-    const int gi = blockIdx.x / maxch, c = blockIdx.x % maxch;
+__device__ inline void st_stats(const GroupDesc* __restrict__ groups, int gi, int c) {
     const GroupDesc& g = groups[gi];
     GroupState* st = g.st;
     if (c >= g.nchunk || st->done) return;
@@ -475,8 +474,11 @@ __global__ void __launch_bounds__(kChunkThreads) k_st_stats(const GroupDesc* __r
     }
 }
 
-__global__ void __launch_bounds__(kChunkThreads) k_st_search(const GroupDesc* __restrict__ groups, int maxch, int it) {
-    const int gi = blockIdx.x / maxch, c = blockIdx.x % maxch;
+__global__ void __launch_bounds__(kChunkThreads) k_st_stats(const GroupDesc* __restrict__ groups, int maxch) {
+    st_stats(groups, blockIdx.x / maxch, blockIdx.x % maxch);
+}
+
+__device__ inline void st_search(const GroupDesc* __restrict__ groups, int gi, int c, int it) {
     const GroupDesc& g = groups[gi];
     GroupState* st = g.st;
     if (c >= g.nchunk || st->done) return;
@@ -522,6 +524,10 @@ __global__ void __launch_bounds__(kChunkThreads) k_st_search(const GroupDesc* __
     }
 }
 
+__global__ void __launch_bounds__(kChunkThreads) k_st_search(const GroupDesc* __restrict__ groups, int maxch, int it) {
+    st_search(groups, blockIdx.x / maxch, blockIdx.x % maxch, it);
+}
+
 // Groups whose search did not converge within the launches: the full search in one
 // workgroup (bisect() from the start; not seen in practice).
 __global__ void __launch_bounds__(kStageThreads) k_st_finish(const GroupDesc* __restrict__ groups) {
@@ -545,8 +551,7 @@ __global__ void __launch_bounds__(kStageThreads) k_st_finish(const GroupDesc* __
     }
 }
 
-__global__ void __launch_bounds__(kChunkThreads) k_st_weights(const GroupDesc* __restrict__ groups, int maxch) {
-    const int gi = blockIdx.x / maxch, c = blockIdx.x % maxch;
+__device__ inline void st_weights(const GroupDesc* __restrict__ groups, int gi, int c) {
     const GroupDesc& g = groups[gi];
     if (c >= g.nchunk || g.st->done) return;
     __shared__ double red[kStagePartVals][kChunkWaves];
@@ -562,11 +567,13 @@ __global__ void __launch_bounds__(kChunkThreads) k_st_weights(const GroupDesc* _
     }
 }
 
+__global__ void __launch_bounds__(kChunkThreads) k_st_weights(const GroupDesc* __restrict__ groups, int maxch) {
+    st_weights(groups, blockIdx.x / maxch, blockIdx.x % maxch);
+}
+
 // Evidence update (chunk 0) and the quantised weights with their scan inside the chunk.
 // With unit_sum set the weights in the CDF buffer are taken as already normalised.
-__global__ void __launch_bounds__(kChunkThreads) k_st_quantise(const GroupDesc* __restrict__ groups, int maxch,
-                                                               int unit_sum) {
-    const int gi = blockIdx.x / maxch, c = blockIdx.x % maxch;
+__device__ inline void st_quantise(const GroupDesc* __restrict__ groups, int gi, int c, int unit_sum) {
     const GroupDesc& g = groups[gi];
     GroupState* st = g.st;
     if (c >= g.nchunk || st->done) return;
@@ -645,10 +652,15 @@ __global__ void __launch_bounds__(kChunkThreads) k_st_quantise(const GroupDesc* 
     }
 }
 
+__global__ void __launch_bounds__(kChunkThreads) k_st_quantise(const GroupDesc* __restrict__ groups, int maxch,
+                                                               int unit_sum) {
+    st_quantise(groups, blockIdx.x / maxch, blockIdx.x % maxch, unit_sum);
+}
+
 // Exclusive prefix of the chunk totals, in place, and their grand total Q (kept in the
 // final search state).
-__global__ void __launch_bounds__(kChunkThreads) k_st_offsets(const GroupDesc* __restrict__ groups) {
-    const GroupDesc& g = groups[blockIdx.x];
+__device__ inline void st_offsets(const GroupDesc* __restrict__ groups, int gi) {
+    const GroupDesc& g = groups[gi];
     if (g.st->done) return;
     __shared__ unsigned long long s_scan[kChunkWaves];
     __shared__ unsigned long long s_carry;
@@ -678,11 +690,14 @@ __global__ void __launch_bounds__(kChunkThreads) k_st_offsets(const GroupDesc* _
     if (threadIdx.x == 0) nst_buf(g, kNewtonLaunches)->Q = s_carry;
 }
 
+__global__ void __launch_bounds__(kChunkThreads) k_st_offsets(const GroupDesc* __restrict__ groups) {
+    st_offsets(groups, blockIdx.x);
+}
+
 // Ancestor of position m and the gather of its state.  r_fixed >= 0 replaces the drawn
 // uniform (hook).  anc (optional) receives the ancestors.
-__global__ void __launch_bounds__(kChunkThreads) k_st_resample(const GroupDesc* __restrict__ groups, int mblocks,
-                                                               int64_t r_fixed, int32_t* __restrict__ anc) {
-    const int gi = blockIdx.x / mblocks, mb = blockIdx.x % mblocks;
+__device__ inline void st_resample(const GroupDesc* __restrict__ groups, int gi, int mb, int64_t r_fixed,
+                                   int32_t* __restrict__ anc) {
     const GroupDesc& g = groups[gi];
     GroupState* st = g.st;
     const int m = mb * kChunkThreads + static_cast<int>(threadIdx.x);
@@ -712,13 +727,17 @@ __global__ void __launch_bounds__(kChunkThreads) k_st_resample(const GroupDesc* 
     }
 }
 
+__global__ void __launch_bounds__(kChunkThreads) k_st_resample(const GroupDesc* __restrict__ groups, int mblocks,
+                                                               int64_t r_fixed, int32_t* __restrict__ anc) {
+    st_resample(groups, blockIdx.x / mblocks, blockIdx.x % mblocks, r_fixed, anc);
+}
+
 // Random-walk scales s_j = lambda_j * sd_j over the resampled states: one 256-thread
 // workgroup per (group, component) (a fixed shape, so every path sums in the same order
 // and gives the same bits), two passes (the mean, then the squared deviations) in FP64 with
 // four accumulators per thread to keep several loads in flight.
-__global__ void __launch_bounds__(kChunkThreads) k_st_steps(const GroupDesc* __restrict__ groups, int dmax) {
+__device__ inline void st_steps(const GroupDesc* __restrict__ groups, int gi, int j) {
     __shared__ double red[1][kChunkWaves];
-    const int gi = blockIdx.x / dmax, j = blockIdx.x % dmax;
     const GroupDesc& g = groups[gi];
     if (g.st->done || j >= g.d) return;
     if (g.prior[j].kind == SMC_PRIOR_FIXED) {
@@ -750,6 +769,36 @@ __global__ void __launch_bounds__(kChunkThreads) k_st_steps(const GroupDesc* __r
     const double sd = sqrt(v[0] / M);
     const double fl = 1e-12 * (fabs(mean) + 1.0);
     if (threadIdx.x == 0) g.step[j] = static_cast<float>(g.lambda[j] * (sd > fl ? sd : fl));
+}
+
+__global__ void __launch_bounds__(kChunkThreads) k_st_steps(const GroupDesc* __restrict__ groups, int dmax) {
+    st_steps(groups, blockIdx.x / dmax, blockIdx.x % dmax);
+}
+
+// ------------------------------------------------------------ single-chunk stages
+// Groups of at most kStageChunk particles (one chunk) and at most kStageChunk resampled
+// positions: the steps above up to the resampling, in one workgroup per group, as the
+// bodies of the launches they replace, run one after another with a barrier between them
+// (the writes of one are the reads of the next, within the workgroup).  Every body sums in
+// the order of its own launch, so the results are those of the chunk-parallel launches bit
+// for bit; the stage costs four launches instead of seventeen (the step sizes keep their
+// own launch, one workgroup per component).
+__global__ void __launch_bounds__(kChunkThreads) k_st_pre1(const GroupDesc* __restrict__ groups) {
+    st_stats(groups, blockIdx.x, 0);
+    for (int it = 0; it < kNewtonLaunches; ++it) {
+        __syncthreads();
+        st_search(groups, blockIdx.x, 0, it);
+    }
+}
+
+__global__ void __launch_bounds__(kChunkThreads) k_st_post1(const GroupDesc* __restrict__ groups, int mblocks) {
+    st_weights(groups, blockIdx.x, 0);
+    __syncthreads();
+    st_quantise(groups, blockIdx.x, 0, 0);
+    __syncthreads();
+    st_offsets(groups, blockIdx.x);
+    __syncthreads();
+    for (int mb = 0; mb < mblocks; ++mb) st_resample(groups, blockIdx.x, mb, int64_t{-1}, nullptr);
 }
 
 // ------------------------------------------------------------------ hook kernels
@@ -793,6 +842,16 @@ hipError_t launch_draw_items(const GroupDesc* groups, const MoveWork* items, int
 hipError_t launch_stage(const StageLaunch& L, hipStream_t s) {
     if (L.n_groups <= 0) return hipSuccess;
     const int maxch = (L.max_p + kStageChunk - 1) / kStageChunk;
+    if (maxch == 1 && L.max_m <= kStageChunk) {
+        const dim3 ng(static_cast<unsigned>(L.n_groups));
+        hipLaunchKernelGGL(k_st_pre1, ng, dim3(kChunkThreads), 0, s, L.groups);
+        hipLaunchKernelGGL(k_st_finish, ng, dim3(kStageThreads), 0, s, L.groups);
+        hipLaunchKernelGGL(k_st_post1, ng, dim3(kChunkThreads), 0, s, L.groups,
+                           (L.max_m + kChunkThreads - 1) / kChunkThreads);
+        const int dmax = std::max(L.max_d, 1);
+        hipLaunchKernelGGL(k_st_steps, dim3(L.n_groups * dmax), dim3(kChunkThreads), 0, s, L.groups, dmax);
+        return hipGetLastError();
+    }
     const dim3 nb(static_cast<unsigned>(L.n_groups * maxch));
     hipLaunchKernelGGL(k_st_stats, nb, dim3(kChunkThreads), 0, s, L.groups, maxch);
     for (int it = 0; it < kNewtonLaunches; ++it)
