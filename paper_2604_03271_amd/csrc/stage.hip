@@ -529,7 +529,8 @@ __global__ void __launch_bounds__(kChunkThreads) k_st_search(const GroupDesc* __
 }
 
 // Groups whose search did not converge within the launches: the full search in one
-// workgroup (bisect() from the start; not seen in practice).
+// workgroup (bisect() from the start; rare: 4 of 125 stages of the N = 201, P = 512
+// three-Gaussian runs, 50-100 us each, an idle launch of ~5 us otherwise).
 __global__ void __launch_bounds__(kStageThreads) k_st_finish(const GroupDesc* __restrict__ groups) {
     const GroupDesc& g = groups[blockIdx.x];
     GroupState* st = g.st;
