@@ -71,13 +71,15 @@ template <int L, int WPC, int PPL>
 struct XrdChain {
     static constexpr int LC = L * WPC;
     static constexpr int TPB = LC > 256 ? LC : 256;   // threads per workgroup
-    // Width factors cached in registers up to 10 points per lane; beyond that they would
-    // spill, and every shape proposal evaluates both widths.
-    static constexpr bool kCW = PPL <= 10;
+    // Width factors cached in registers: W1 at every tile but 14 points per lane (3 waves
+    // per SIMD there: it would spill), W2 up to 10 points per lane (beyond that both would
+    // spill); a factor not cached is formed anew by every shape proposal.
+    static constexpr bool kCW1 = PPL != 14;
+    static constexpr bool kCW2 = PPL <= 10;
     float x[PPL], tn[PPL], y[PPL];
     float D[PPL];
     float S1[PPL], S2[PPL];
-    float W1[PPL], W2[PPL];   // width factors of the current term when it is a peak (kCW)
+    float W1[PPL], W2[PPL];   // width factors of the current term when it is a peak
     bool wbad = false;        // some Caglioti argument of the current peak is not positive
 
     __device__ __forceinline__ void load_points(const GroupDesc& g, int lane) {
@@ -172,11 +174,9 @@ struct XrdChain {
     __device__ __forceinline__ void prop_shape(const XrdC& q, int p, float& e, float& l, bool& bad) const {
         if constexpr (BG) {
             bg_shape(q, p, e, l);
-        } else if constexpr (!kCW) {
-            peak_shape(q, p, e, l, bad);
         } else {
-            const float w1 = MODE == kXrdNewW1 ? peak_w1(q, p, bad) : W1[p];
-            const float w2 = MODE == kXrdNewW2 ? peak_w2(q, p) : W2[p];
+            const float w1 = (MODE == kXrdNewW1 || !kCW1) ? peak_w1(q, p, bad) : W1[p];
+            const float w2 = (MODE == kXrdNewW2 || !kCW2) ? peak_w2(q, p) : W2[p];
             peak_shape_w(q, p, w1, w2, e, l);
         }
     }
@@ -187,7 +187,7 @@ struct XrdChain {
     template <bool BG, int MODE, bool STORE>
     __device__ __forceinline__ float partial_shape_t(const XrdC& q, float2* sl) const {
         float acc = 0.0f;
-        bool bad = !BG && kCW && MODE != kXrdNewW1 && wbad;
+        bool bad = !BG && kCW1 && MODE != kXrdNewW1 && wbad;
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
             float e, l;
@@ -226,10 +226,8 @@ struct XrdChain {
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
             const float w1 = peak_w1(q, p, bad), w2 = peak_w2(q, p);
-            if constexpr (kCW) {
-                W1[p] = w1;
-                W2[p] = w2;
-            }
+            if constexpr (kCW1) W1[p] = w1;
+            if constexpr (kCW2) W2[p] = w2;
             peak_shape_w(q, p, w1, w2, S1[p], S2[p]);
         }
         wbad = bad;
@@ -244,13 +242,13 @@ struct XrdChain {
             return;
         }
         load_shapes(sl);
-        if (is_bg || !kCW) return;
-        if (mode == kXrdNewW1) {
+        if (is_bg) return;
+        if (kCW1 && mode == kXrdNewW1) {
             bool bad = false;
 #pragma unroll
             for (int p = 0; p < PPL; ++p) W1[p] = peak_w1(q, p, bad);
             wbad = bad;
-        } else if (mode == kXrdNewW2) {
+        } else if (kCW2 && mode == kXrdNewW2) {
 #pragma unroll
             for (int p = 0; p < PPL; ++p) W2[p] = peak_w2(q, p);
         }
