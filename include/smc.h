@@ -168,7 +168,8 @@ smc_status smc_evaluation_kinds(const smc_ctx* ctx, uint64_t* out);
 
 /* With options.profile = 1: out (host) [4] = {total ms of move launches, number of move
  * launches, total ms of stage launches, number of stage launches}, measured with HIP events
- * on the context's stream. */
+ * on the context's stream.  Only launches in which some K still had work count (smc_run's
+ * stages launched after every K finished do not); one move launch per stage. */
 smc_status smc_profile(const smc_ctx* ctx, double* out);
 
 /* Tile autotuner: runs `stages` (1..64) tempering stages of this problem with every lane
