@@ -117,8 +117,10 @@ def test_server_admission_under_small_budget():
 
 
 def test_server_mixed_shapes_equal_alone():
-    """N=201 Gaussian-peak (standard, n=10) and N=1001 pseudo-Voigt (waste-free, n=16) requests with
-    their own options in one pool; every result equals the same request run alone."""
+    """N=201 Gaussian-peak (standard, n=10, P=512) and N=1001 pseudo-Voigt (waste-free, n=16,
+    P=8192) requests with their own options in one pool; every result equals the same request
+    run alone.  Alone, a P=512 request's stages take the single-chunk launches; in a pool that
+    also holds P=8192 groups they take the chunk-parallel ones: the same bits either way."""
     torch_cuda()
     say("server mixed shapes")
     srv = native.Server(4 << 30, native.options(n_particles=512, n_moves=10, waste_free=False, seed=9))
@@ -127,7 +129,7 @@ def test_server_mixed_shapes_equal_alone():
         if i % 2 == 0:
             sp, kw = W.gauss3_n201(200 + i), dict(n_particles=512, n_moves=10, waste_free=False, seed=9)
         else:
-            sp, kw = W.pvoigt5_n1001(200 + i), dict(n_particles=2048, n_moves=16, waste_free=True, seed=9)
+            sp, kw = W.pvoigt5_n1001(200 + i), dict(n_particles=8192, n_moves=16, waste_free=True, seed=9)
             sp.k_max = 4
         sp.uid = 700 + i
         reqs.append((sp, kw))

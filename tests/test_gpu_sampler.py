@@ -257,9 +257,11 @@ def test_run_equals_stepping():
 
 
 @pytest.mark.parametrize("cfg,P,wf,n", [("pvoigt5_n1001", 65536, True, 16), ("pvoigt16_poisson_n4096", 16384, True, 16),
-                                        ("gauss3_n201", 512, False, 10)])
+                                        ("gauss3_n201", 512, False, 10), ("gauss3_n201", 4096, False, 10),
+                                        ("gauss3_n201", 4097, False, 10)])
 def test_stage_matches_reference_at_full_size(orc, cfg, P, wf, n):
-    """The stage kernel (spread over several workgroups per K at these sizes) against the
+    """The stage kernels (spread over several workgroups per K, or one per K up to 4096
+    particles: the single-chunk launches, at and just past their limit) against the
     reference's FP64 bisection, ESS and log-sum-exp on the same stage-0 energies."""
     spec = getattr(W, cfg)(0)
     say("stage full size", cfg, P)
