@@ -97,7 +97,10 @@ struct ChainState {
         return r;
     }
 
+    // The background at point p; 0 at padding points, which only the rows from
+    // ppl_before(PPL) on can hold (the tile rule), so the rows before need no mask.
     __device__ __forceinline__ float bg_at(const PeakC& q, int p) const {
+        if (p < ppl_before(PPL)) return bg_eval(x[p], q);
         return x[p] < 1.0e17f ? bg_eval(x[p], q) : 0.0f;
     }
 

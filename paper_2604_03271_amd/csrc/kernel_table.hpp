@@ -7,12 +7,13 @@
 
 #include <hip/hip_runtime.h>
 
+#include "smc_types.hpp"
+
 namespace smc {
 
 constexpr int kNumLaneCfg = 5;            // 16x1, 32x1, 64x1, 64x4, 64x8
 constexpr int kLanesOf[kNumLaneCfg] = {16, 32, 64, 256, 512};
-constexpr int kNumPpl = 16;
-constexpr int kPplOf[kNumPpl] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32};
+// the points-per-lane list (kNumPpl, kPplOf) is in smc_types.hpp: the kernels read it too
 
 // [peak kind][noise kind][lane configuration][points per lane]; noise kind 2 (heteroscedastic,
 // with the Shirley background) exists for pseudo-Voigt peaks, one-wavefront lane

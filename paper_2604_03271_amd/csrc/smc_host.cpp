@@ -175,6 +175,7 @@ Tile choose_tile(const smc_problem& p, int64_t chains, int forced_lanes) {
         const int rows = (n_points + kLanesOf[best] - 1) / kLanesOf[best];
         int pi = 0;
         while (kPplOf[pi] < rows) ++pi;
+        if (n_points <= ppl_before(kPplOf[pi]) * kLanesOf[best]) return t;
         return Tile{best, pi, kLanesOf[best], kPplOf[pi], true};
     }
     // Preference: chains inside one wavefront with at most 16 points per lane (the move
@@ -208,6 +209,8 @@ Tile choose_tile(const smc_problem& p, int64_t chains, int forced_lanes) {
     const int rows = (n_points + lanes - 1) / lanes;
     int pi = 0;
     while (kPplOf[pi] < rows) ++pi;
+    // the kernels take the rows before ppl_before(PPL) as free of padding
+    if (n_points <= ppl_before(kPplOf[pi]) * lanes) return t;
     t.lc = best;
     t.pi = pi;
     t.lanes = lanes;

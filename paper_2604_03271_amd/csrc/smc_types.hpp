@@ -37,6 +37,18 @@ struct GroupState {
 
 constexpr int kTraceCols = 6;  // beta, delta, ess, lse, logz, acceptance
 
+// Points per lane of the move / energy tiles.  A tile of PPL points per lane serves the N
+// with ceil(N / lanes) in (ppl_before(PPL), PPL]: its first ppl_before(PPL) rows of points
+// are full for every such N, only the rows after them can hold padding.
+constexpr int kNumPpl = 16;
+constexpr int kPplOf[kNumPpl] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32};
+constexpr int ppl_before(int ppl) {
+    int b = 0;
+    for (int i = 0; i < kNumPpl; ++i)
+        if (kPplOf[i] < ppl) b = kPplOf[i];
+    return b;
+}
+
 // The stage kernels split each group's P particles into chunks of kStageChunk.
 constexpr int kStageChunk = 4096;
 constexpr int kStagePartVals = 6;  // partial sums per chunk
