@@ -637,6 +637,7 @@ extern "C" smc_status smc_reset(smc_ctx* c, uint64_t seed) {
         upload_group_tables(c->spec, c->groups, 0, c->groups.size(), s, keep) != hipSuccess)
         return SMC_EDEVICE;
     c->finished = false;
+    c->n_ev_move = c->n_ev_stage = 0;   // event pairs of a run that ended in an error are dropped
     smc_status st = stage0(c);
     if (st != SMC_OK) return st;
     return hipStreamSynchronize(s) == hipSuccess ? SMC_OK : SMC_EDEVICE;
