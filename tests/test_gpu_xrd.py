@@ -88,8 +88,12 @@ def test_init_draws_follow_reference_streams(orc):
     assert np.allclose(e[sub][fin], ref[fin], rtol=2e-5)
 
 
+# tiles: 256 lanes x 4 and 64 x 7 (both width factors cached), 256 x 12, 16 and 20 and 512 x 20
+# (W1 cached), 256 x 14 (neither)
 @pytest.mark.parametrize("n,K,M,nm,wf,beta", [(1000, 3, 128, 4, True, 1e-4), (400, 2, 64, 2, False, 1e-3),
-                                              (5120, 1, 96, 2, True, 1e-2), (10000, 3, 40, 2, True, 1e-4)])
+                                              (5120, 1, 96, 2, True, 1e-2), (10000, 3, 40, 2, True, 1e-4),
+                                              (3000, 2, 64, 2, True, 1e-4), (3500, 2, 64, 2, True, 1e-4),
+                                              (4000, 2, 64, 2, False, 1e-3)])
 def test_move_matches_reference(orc, n, K, M, nm, wf, beta):
     torch = torch_cuda()
     spec = _spec(n, K, index=4)
