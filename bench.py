@@ -164,19 +164,102 @@ def cpu_baseline(spec, K, seconds_target=10.0):
                       f"single thread: {M1} chains, {ne1} evaluations, {dt1:.2f} s"}
 
 
-def batched(native, workloads, n_spectra, P=8192, plain_sample=4):
-    """Uneven batch: n_spectra spectra of N~U{200..4000}, every K = 1..8, in one pool (captured stage replayed).
-    The plain comparator runs a few of the same spectra one at a time, one K at a time."""
+def config1_oracle(seconds_cap=60.0):
+    """The FP64 reference end to end on the N=201 three-Gaussian spectrum (K=1..4, P=512, standard
+    n=10): one whole spectrum, every K, on all host threads."""
+    import oracle
+    from paper_2604_03271_amd import workloads
+    spec = workloads.gauss3_n201(0)
+    opr = oracle.Problem(spec)
+    t0 = time.perf_counter()
+    runs = 0
+    while True:
+        for K in range(spec.k_min, spec.k_max + 1):
+            oracle.run(opr, K, 512, 10, False, 1 + runs, spec.uid)
+        runs += 1
+        dt = time.perf_counter() - t0
+        if dt > 0.1 * seconds_cap or runs >= 5:
+            break
+    return {"spectra_per_s": runs / dt, "runs": runs, "seconds": dt, "threads": oracle.num_threads()}
+
+
+def fp64_check(native, spec, opt, sampler, orc_seeds=None):
+    """Error of the GPU results against the FP64 reference on the bench spectrum:
+    * energies: FP32 energies the GPU carries for its final particles of every K, against the
+      reference's FP64 energies of the same FP32 parameters (64 particles per K);
+    * the first tempering stage of every K (FP64 on the GPU): increment, ESS and evidence increment
+      against the reference's on the GPU's own stage-0 energies;
+    * log Z per K: 10 GPU seeds at the evidence-parity particle count against the reference's
+      stored 10-seed values (tests/golden/oracle_evidences.json), mean difference and its standard
+      error."""
+    import math
+    import oracle
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import oracle_runs
+    opr = oracle.Problem(spec)
+    C = native.Problem(spec).energy_constant()
+    ks = list(range(spec.k_min, spec.k_max + 1))
+    rel = 0.0
+    for K in ks:
+        th, e = sampler.particles(K)
+        idx = np.linspace(0, th.shape[1] - 1, 64).astype(int)
+        ref = np.array([oracle.energy(opr, K, th[:, i].astype(np.float64)) for i in idx]) - C
+        rel = max(rel, float(np.max(np.abs(e[idx].astype(np.float64) - ref) / np.abs(ref))))
+    sampler.reset(12345)
+    e0 = {K: sampler.particles(K)[1].astype(np.float64) for K in ks}
+    sampler.step()
+    d_err, ess_err, lz_err = 0.0, 0.0, 0.0
+    P = opt.n_particles
+    for K in ks:
+        tr = sampler.trace(K)
+        d = tr["beta"][0]
+        d_ref = oracle.next_delta(e0[K], 0.0, opt.ess_frac, opt.bisect_iters)
+        ess_ref, lse_ref = oracle.ess(e0[K], d)
+        d_err = max(d_err, abs(d - d_ref) / d_ref)
+        ess_err = max(ess_err, abs(tr["ess"][0] / ess_ref - 1.0))
+        lz_err = max(lz_err, abs(tr["logz"][0] - (lse_ref - math.log(P) - d * C)))
+    out = {"energy_max_rel_err": rel, "energy_sample": f"64 final particles per K, K={ks[0]}..{ks[-1]}",
+           "stage1_delta_max_rel_err": d_err, "stage1_ess_max_rel_err": ess_err,
+           "stage1_logz_increment_max_abs_err": lz_err}
+    case = oracle_runs.CASES.get("pvoigt5_n1001")
+    rows = oracle_runs.partial("pvoigt5_n1001")
+    if case and len(rows) == len(case["seeds"]):
+        o = np.array(rows)
+        g = []
+        for seed in case["seeds"]:
+            s = native.Sampler(spec, native.options(seed=seed, n_particles=case["P"], n_moves=case["n"],
+                                                    waste_free=case["wf"]))
+            s.run()
+            g.append(s.log_evidence())
+            s.close()
+        g = np.array(g)
+        diff = g.mean(0) - o.mean(0)
+        se = np.sqrt(g.var(0, ddof=1) / len(g) + o.var(0, ddof=1) / len(o))
+        out["log_evidence"] = {"P": case["P"], "seeds": len(g), "K": case["Ks"],
+                               "diff_nats": diff.round(4).tolist(), "se_nats": se.round(4).tolist(),
+                               "within_3se": bool(np.all(np.abs(diff) <= 3 * se)),
+                               "same_argmax": bool(np.argmax(g.mean(0)) == np.argmax(o.mean(0)))}
+    return out
+
+
+def batched(native, workloads, n_spectra, P=8192, plain_sample=0):
+    """Uneven batch: n_spectra spectra of N~U{200..4000}, every K = 1..8, all groups in one pool (the
+    stage's launches captured once and replayed).  The plain comparator runs the same spectra (all of
+    them, or the first plain_sample) one at a time, one K at a time, with the same kernels."""
     import torch
     specs = workloads.uneven_batch(n_spectra=n_spectra)
     opt = native.options(n_particles=P, n_moves=16, waste_free=True, seed=3)
+    progress(f"batch of {n_spectra} spectra")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    native.smc_batch_run(specs, opt)
+    lz = native.smc_batch_run(specs, opt)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    n_plain = plain_sample or n_spectra
     tp = 0.0
-    for sp in specs[:plain_sample]:
+    for i, sp in enumerate(specs[:n_plain]):
+        if i % 64 == 0:
+            progress(f"plain comparator: spectrum {i + 1}/{n_plain}")
         s = native.Sampler(sp, native.options(n_particles=P, n_moves=16, waste_free=True, seed=3, plain=True))
         torch.cuda.synchronize()
         ts = time.perf_counter()
@@ -184,11 +267,14 @@ def batched(native, workloads, n_spectra, P=8192, plain_sample=4):
         torch.cuda.synchronize()
         tp += time.perf_counter() - ts
         s.close()
+    hit = np.mean([int(np.argmax(z)) + sp.k_min == sp.truth["K"] for z, sp in zip(lz, specs)])
     return {"workload": f"uneven batch: {n_spectra} spectra, N~U{{200..4000}}, Gaussian/pseudo-Voigt, "
                         f"K=1..8, P={P}, waste-free n=16",
             "spectra_per_s": n_spectra / dt, "batch_s": dt,
-            "plain_gpu_spectra_per_s": plain_sample / tp,
-            "plain_note": f"same kernels, one spectrum and one K at a time, measured on {plain_sample} of them"}
+            "plain_gpu_spectra_per_s": n_plain / tp, "plain_s": tp, "plain_spectra": n_plain,
+            "speedup_vs_plain": (n_spectra / dt) / (n_plain / tp),
+            "best_k_is_true_k": float(hit),
+            "plain_note": "same kernels, one spectrum and one K at a time (one launch per K per stage)"}
 
 
 def progress(*a):
@@ -216,7 +302,7 @@ def served(native, workloads, n_arrivals, rate, budget=64 << 30):
         for r in srv.poll(1):
             got[r["id"]] = r
             lat.append(r["latency_s"])
-            if len(got) % 50 == 0:
+            if len(got) % 100 == 0:
                 progress(f"served {len(got)}/{n_arrivals} at rate {rate}")
     dur = time.perf_counter() - t0
     srv.close()
@@ -225,7 +311,18 @@ def served(native, workloads, n_arrivals, rate, budget=64 << 30):
                         "(P=512, standard n=10), 30% N=1001 pseudo-Voigt (P=65536, waste-free n=16)",
             "spectra_per_s": n_arrivals / dur, "duration_s": dur,
             "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-            "offered_per_s": rate}
+            "offered_per_s": rate, "arrivals": n_arrivals}
+
+
+def served_sweep(native, workloads, rates, n_arrivals):
+    """The stream at lower offered rates: p99 stays bounded while the server keeps up with the
+    arrivals (served rate >= 0.95 x offered over the window); the largest such rate is reported."""
+    runs = [served(native, workloads, n_arrivals, float(r)) for r in rates]
+    ok = [r["offered_per_s"] for r in runs if r["spectra_per_s"] >= 0.95 * r["offered_per_s"]]
+    return {"runs": [{"offered_per_s": r["offered_per_s"], "spectra_per_s": r["spectra_per_s"],
+                      "latency_s": r["latency_s"], "arrivals": r["arrivals"]} for r in runs],
+            "max_rate_p99_bounded": max(ok) if ok else None,
+            "criterion": "served rate >= 0.95 x offered rate over the window (the queue does not grow)"}
 
 
 def _workload(name, native_options, workloads, particles, lanes=0):
@@ -280,13 +377,23 @@ def main():
     ap.add_argument("--tune", action="store_true", help="lanes per chain from the library's autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--batch", type=int, default=0, help="also run the uneven batch with this many spectra")
-    ap.add_argument("--serve", type=int, default=0, help="also serve this many arrivals of the Poisson stream")
+    ap.add_argument("--batch", type=int, default=-1,
+                    help="uneven batch of this many spectra (0: none; default 512 with the default workload)")
+    ap.add_argument("--plain-sample", type=int, default=0,
+                    help="spectra of the batch run one at a time for the plain comparator (0: all)")
+    ap.add_argument("--serve", type=int, default=-1,
+                    help="arrivals of the Poisson stream to serve (0: none; default 2000 with the default workload)")
     ap.add_argument("--rate", type=float, default=200.0)
-    ap.add_argument("--rates", default="", help="comma-separated arrival rates: serve --serve arrivals at each")
+    ap.add_argument("--rates", default="10,20,30,40",
+                    help="comma-separated lower arrival rates, each served with --sweep-arrivals arrivals")
+    ap.add_argument("--sweep-arrivals", type=int, default=200)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one device-to-device copy of this many bytes (calibrates HBM counters)")
     args = ap.parse_args()
+    if args.batch < 0:
+        args.batch = 512 if args.workload == "xps-pv" and not args.particles else 0
+    if args.serve < 0:
+        args.serve = 2000 if args.workload == "xps-pv" and not args.particles else 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the sampler's groups are independent and the bench "
               "measures one GPU's share; use --gpus 1", file=sys.stderr)
@@ -415,13 +522,31 @@ def main():
                             "note": "same kernels, one K at a time, one launch per K per stage"}
         sp.close()
     if args.batch:
-        out["batched"] = batched(native, workloads, args.batch)
+        out["batched"] = batched(native, workloads, args.batch, plain_sample=args.plain_sample)
     if args.serve:
         out["served"] = served(native, workloads, args.serve, args.rate)
         if args.rates:
-            out["served_sweep"] = [served(native, workloads, args.serve, float(r)) for r in args.rates.split(",")]
+            out["served_sweep"] = served_sweep(native, workloads, args.rates.split(","), args.sweep_arrivals)
+    if args.workload == "xps-pv" and P == 65536 and not args.no_cpu_baseline:
+        # the N=201 spectrum end to end on the GPU (the reference's end-to-end timing is beside it)
+        s1 = native.Sampler(workloads.gauss3_n201(0), native.options(n_particles=512, n_moves=10, waste_free=False))
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for k in range(20):
+            s1.reset(k + 1).run()
+        torch.cuda.synchronize()
+        out["config1"] = {"workload": "N=201, 3 Gaussian peaks, K=1..4, P=512, standard n=10",
+                          "gpu_spectra_per_s": 20 / (time.perf_counter() - ts)}
+        s1.close()
     if not args.no_cpu_baseline:
+        # the reference's leg: its timing on the host, and the FP64 check of the GPU's results
+        progress("reference (CPU) leg")
         out["cpu_baseline"] = cpu_baseline(spec, 5 if args.workload == "xps-pv" else spec.truth["K"])
+        if "config1" in out:
+            out["config1"]["oracle_end_to_end"] = config1_oracle()
+            out["config1"]["gpu_over_oracle"] = (out["config1"]["gpu_spectra_per_s"]
+                                                 / out["config1"]["oracle_end_to_end"]["spectra_per_s"])
+        out["fp64_check"] = fp64_check(native, spec, opt, s)
     s.close()
     print(json.dumps(out), flush=True)
 

@@ -310,6 +310,18 @@ smc_status smc_kernel_resample(const double* weights, int32_t P, int32_t M, uint
 smc_status smc_kernel_summary(const float* theta, int32_t d, int32_t P, int32_t n_peaks, int32_t np,
                               const double* probs, int32_t n_probs, double* mean, double* quant, void* hip_stream);
 
+/* Step-size adaptation and step sizes of candidate K (Sec. II.B.4; the rule itself is a
+ * reading, stated at the top of this file), as one tempering stage computes them: first
+ * lambda_j <- clamp(lambda_j exp(acc_j / (M n_moves) - 0.44), 0.01, 10) for every free
+ * component j, with acc (device) [d] the accepted proposals of the last move (cleared to 0
+ * on return); then step (device) [d] FP32 = lambda_j * sd_j, sd_j the FP64 population
+ * standard deviation of component j over the M resampled states start_soa (device) [d][M]
+ * (floored at 1e-12 (|mean_j| + 1)).  lambda (device) [d] FP64 is read and updated in place.
+ * Components whose prior is FIXED keep their lambda and get step 0.  Errors: SMC_EINVAL
+ * (NULL buffers, K, M or n_moves < 1, an invalid problem), SMC_ENOMEM, SMC_EDEVICE. */
+smc_status smc_kernel_step_sizes(const smc_problem* prob, int32_t K, const float* start_soa, int32_t M,
+                                 int32_t n_moves, double* lambda, uint32_t* acc, float* step, void* stream);
+
 /* One MH move of candidate K at inverse temperature beta: M start states start_soa
  * (device) [d][M] with energies start_e [M], step sizes step (device) [d]; outputs
  * out_soa (device) [d][P] and out_e [P] with P = M*n (waste-free) or M (standard), and

@@ -271,6 +271,23 @@ extern "C" smc_status smc_kernel_move(const smc_problem* prob, int32_t K, const 
     return finish(s);
 }
 
+extern "C" smc_status smc_kernel_step_sizes(const smc_problem* prob, int32_t K, const float* start_soa, int32_t M,
+                                            int32_t n_moves, double* lambda, uint32_t* acc, float* step,
+                                            void* stream) {
+    if (!prob || K < 1 || M < 1 || n_moves < 1 || !start_soa || !lambda || !acc || !step) return SMC_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HookGroup h;
+    smc_status st = make_hook_group(h, prob, K, M, M, n_moves, 0, M, 0, 0.0, 1, 0, s);
+    if (st != SMC_OK) return st;
+    h.g.start = const_cast<float*>(start_soa);
+    h.g.lambda = lambda;
+    h.g.acc = acc;
+    h.g.step = step;
+    if ((st = upload_desc(h, s)) != SMC_OK) return st;
+    if (launch_steps_hook(h.d_group, h.g.d, s) != hipSuccess) return SMC_EDEVICE;
+    return finish(s);
+}
+
 extern "C" smc_status smc_kernel_summary(const float* theta, int32_t d, int32_t P, int32_t n_peaks, int32_t np,
                                          const double* probs, int32_t n_probs, double* mean, double* quant,
                                          void* hip_stream) {

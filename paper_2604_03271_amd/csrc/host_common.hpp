@@ -89,6 +89,7 @@ struct StageLaunch {
 hipError_t launch_stage(const StageLaunch& L, hipStream_t s);
 hipError_t launch_search_hook(const GroupDesc* group, int P, hipStream_t s);
 hipError_t launch_resample_hook(const GroupDesc* group, int P, int M, uint32_t r, int32_t* anc, hipStream_t s);
+hipError_t launch_steps_hook(const GroupDesc* group, int d, hipStream_t s);
 int stage_final_parity();
 size_t stage_scratch_bytes(int P);
 bool carve_stage_scratch(Arena& a, int P, GroupDesc& g);

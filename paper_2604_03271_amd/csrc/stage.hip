@@ -409,32 +409,40 @@ __device__ inline void chunk_range(const GroupDesc& g, int c, int& i0, int& i1) 
     i1 = min(g.P, i0 + kStageChunk);
 }
 
+// Step-size adaptation after a move (one workgroup, thread j for component j):
+// lambda_j <- clamp(lambda_j exp(acc_j - 0.44), 0.01, 10) with acc_j the acceptance rate of
+// component j over the move's M n proposals, the counters cleared, and the stage's mean
+// acceptance over the free components into the trace.  Before the first move (stage 0) only
+// the counters are cleared.
+__device__ inline void st_adapt(const GroupDesc& g, int stage_prev, double (*red)[kChunkWaves]) {
+    if (stage_prev > 0) {
+        const double props = static_cast<double>(g.M) * g.n_moves;
+        double v[2] = {0.0, 0.0};   // sum of acceptance rates, free components
+        for (int j = threadIdx.x; j < g.d; j += kChunkThreads) {
+            if (g.prior[j].kind == SMC_PRIOR_FIXED) continue;
+            const double a = g.acc[j] / props;
+            v[0] += a;
+            v[1] += 1.0;
+            g.lambda[j] = fmin(10.0, fmax(0.01, g.lambda[j] * exp(a - 0.44)));
+            g.acc[j] = 0u;
+        }
+        chunk_block_sum<2>(v, red);
+        if (threadIdx.x == 0 && stage_prev <= g.max_stages)
+            g.trace[(stage_prev - 1) * kTraceCols + 5] = v[1] > 0.0 ? v[0] / v[1] : 0.0;
+    } else {
+        for (int j = threadIdx.x; j < g.d; j += kChunkThreads) g.acc[j] = 0u;
+    }
+}
+
 __device__ inline void st_stats(const GroupDesc* __restrict__ groups, int gi, int c) {
     const GroupDesc& g = groups[gi];
     GroupState* st = g.st;
     if (c >= g.nchunk || st->done) return;
     __shared__ double red[kStagePartVals][kChunkWaves];
     if (c == 0) {
-        // lambda_j <- clamp(lambda_j exp(acc_j - 0.44), 0.01, 10) after a move (thread j), the
-        // stage's mean acceptance into the trace; end finished groups
+        // step sizes adapt to the last move; end finished groups
         const int stage_prev = st->stage;
-        if (stage_prev > 0) {
-            const double props = static_cast<double>(g.M) * g.n_moves;
-            double v[2] = {0.0, 0.0};   // sum of acceptance rates, free components
-            for (int j = threadIdx.x; j < g.d; j += kChunkThreads) {
-                if (g.prior[j].kind == SMC_PRIOR_FIXED) continue;
-                const double a = g.acc[j] / props;
-                v[0] += a;
-                v[1] += 1.0;
-                g.lambda[j] = fmin(10.0, fmax(0.01, g.lambda[j] * exp(a - 0.44)));
-                g.acc[j] = 0u;
-            }
-            chunk_block_sum<2>(v, red);
-            if (threadIdx.x == 0 && stage_prev <= g.max_stages)
-                g.trace[(stage_prev - 1) * kTraceCols + 5] = v[1] > 0.0 ? v[0] / v[1] : 0.0;
-        } else {
-            for (int j = threadIdx.x; j < g.d; j += kChunkThreads) g.acc[j] = 0u;
-        }
+        st_adapt(g, stage_prev, red);
         if (threadIdx.x == 0 && (st->beta >= 1.0 || stage_prev >= g.max_stages)) {
             if (st->beta < 1.0) st->status = SMC_ENUMERIC;
             st->done = 1;
@@ -776,6 +784,12 @@ __global__ void __launch_bounds__(kChunkThreads) k_st_steps(const GroupDesc* __r
     st_steps(groups, blockIdx.x / dmax, blockIdx.x % dmax);
 }
 
+// Hook: the adaptation of st_stats on its own (one group, stage index > 0).
+__global__ void __launch_bounds__(kChunkThreads) k_st_adapt(const GroupDesc* __restrict__ groups) {
+    __shared__ double red[kStagePartVals][kChunkWaves];
+    st_adapt(groups[0], groups[0].st->stage, red);
+}
+
 // ------------------------------------------------------------ single-chunk stages
 // Groups of at most kStageChunk particles (one chunk) and at most kStageChunk resampled
 // positions: the steps above up to the resampling, in one workgroup per group, as the
@@ -886,6 +900,12 @@ hipError_t launch_resample_hook(const GroupDesc* group, int P, int M, uint32_t r
     hipLaunchKernelGGL(k_st_offsets, dim3(1), dim3(kChunkThreads), 0, s, group);
     const int mblocks = (M + kChunkThreads - 1) / kChunkThreads;
     hipLaunchKernelGGL(k_st_resample, dim3(mblocks), dim3(kChunkThreads), 0, s, group, mblocks, int64_t{r}, anc);
+    return hipGetLastError();
+}
+
+hipError_t launch_steps_hook(const GroupDesc* group, int d, hipStream_t s) {
+    hipLaunchKernelGGL(k_st_adapt, dim3(1), dim3(kChunkThreads), 0, s, group);
+    hipLaunchKernelGGL(k_st_steps, dim3(std::max(d, 1)), dim3(kChunkThreads), 0, s, group, std::max(d, 1));
     return hipGetLastError();
 }
 

@@ -122,6 +122,7 @@ _SIGNATURES = {
     "smc_kernel_resample": (c_i32, [c_vp, c_i32, c_i32, c_u32, c_vp, c_vp]),
     "smc_kernel_move": (c_i32, [P(smc_problem), c_i32, c_vp, c_vp, c_i32, c_i32, c_i32, c_d, c_u64, c_u32,
                                 c_vp, c_vp, c_vp, c_vp, c_i32, c_vp]),
+    "smc_kernel_step_sizes": (c_i32, [P(smc_problem), c_i32, c_vp, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp]),
 }
 
 
@@ -503,6 +504,14 @@ def smc_kernel_summary(theta, d: int, P: int, probs, n_peaks: int = 0, np_: int 
     check(lib().smc_kernel_summary(_ptr(theta), d, P, n_peaks, np_, _pd(pr), len(pr), _pd(mean), _pd(q),
                                    _stream_ptr(stream)), "smc_kernel_summary")
     return mean, q[:len(pr)]
+
+
+def smc_kernel_step_sizes(problem: Problem, K: int, start, M: int, n_moves: int, lam, acc, step,
+                          stream=None) -> None:
+    """start (device) [d][M] FP32, lam (device) [d] FP64 updated in place, acc (device) [d] u32
+    (cleared), step (device) [d] FP32 out."""
+    check(lib().smc_kernel_step_sizes(problem.ref, K, _ptr(start), M, n_moves, _ptr(lam), _ptr(acc), _ptr(step),
+                                      _stream_ptr(stream)), "smc_kernel_step_sizes")
 
 
 def smc_kernel_move(problem: Problem, K: int, start, start_e, n: int, waste_free: bool, beta: float, seed: int,

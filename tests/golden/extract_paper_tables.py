@@ -7,7 +7,8 @@ spectral_true_K3, spectral_true_K10, spectral_true_K30) and App. E (xrd_true_pha
 xrd_true_bg), the prior tables spectral_priors and xrd_priors (constant entries), and the
 heteroscedastic noise parameters of App. D.
 
-Usage: python tests/golden/extract_paper_tables.py /root/reference/PAPER.md
+Usage: python tests/golden/extract_paper_tables.py <file holding the LaTeX source of the
+paper's App. B, D and E tables>
 """
 import json
 import os

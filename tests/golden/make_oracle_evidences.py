@@ -6,8 +6,10 @@ root after any change to the oracle or to the input generators:
 
     python tests/golden/make_oracle_evidences.py [case ...]
 
-With case names, only those cases are recomputed; the others are kept when the
-sources hash still matches.
+With case names, only those cases are computed; the others are kept when the
+sources hash still matches.  The file is rewritten after every seed, so an
+interrupted run continues from the seeds already stored (a case is used by the
+tests only once all its seeds are there).
 """
 import json
 import os
@@ -23,6 +25,13 @@ import oracle  # noqa: E402
 import oracle_runs as R  # noqa: E402
 
 
+def _write(doc):
+    tmp = R.STORE + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(doc, f, indent=1)
+    os.replace(tmp, R.STORE)
+
+
 def main(names):
     h = R.sources_hash()
     doc = R.stored() or {"cases": {}}
@@ -33,13 +42,21 @@ def main(names):
     oracle.lib()
     for name in names or list(R.CASES):
         c = R.CASES[name]
+        old = doc["cases"].get(name)
+        done = old["log_evidence"] if old is not None and R._same_case(old, c) else []
+        spent = old.get("seconds", 0.0) if done else 0.0
         t0 = time.time()
-        lz = R.compute(oracle, name, progress=lambda *a: print(*a, flush=True))
-        doc["cases"][name] = {"Ks": c["Ks"], "seeds": c["seeds"], "P": c["P"], "n": c["n"], "wf": c["wf"],
-                              "offset": c["offset"], "log_evidence": lz.tolist(),
-                              "threads": oracle.num_threads(), "seconds": round(time.time() - t0, 1)}
-        with open(R.STORE, "w") as f:
-            json.dump(doc, f, indent=1)
+
+        def save(rows):
+            doc["cases"][name] = {"Ks": c["Ks"], "seeds": c["seeds"], "P": c["P"], "n": c["n"], "wf": c["wf"],
+                                  "offset": c["offset"], "log_evidence": [list(map(float, r)) for r in rows],
+                                  "threads": oracle.num_threads(), "seconds": round(spent + time.time() - t0, 1)}
+            _write(doc)
+            print(name, "seeds stored", len(rows), "of", len(c["seeds"]), round(time.time() - t0, 1), "s",
+                  flush=True)
+
+        if len(done) < len(c["seeds"]):
+            R.compute(oracle, name, progress=lambda *a: print(*a, flush=True), done=done, on_seed=save)
         print(name, "done", round(time.time() - t0, 1), "s", flush=True)
 
 

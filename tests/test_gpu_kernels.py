@@ -222,3 +222,59 @@ def test_resample_bit_exact(orc, P, M, kind):
         anc = torch.zeros(M, dtype=torch.int32, device="cuda")
         native.smc_kernel_resample(dev(W_, torch.float64), M, r, anc)
         assert np.array_equal(anc.cpu().numpy(), orc.resample(W_, M, r))
+
+
+# ------------------------------------------------------------------ step sizes (Sec. II.B.4)
+
+def _component_prior(spec, K, j):
+    """Prior (kind, a, b) of component j of the K-peak model: peak parameters in peak order,
+    then the background's."""
+    npk = {"gauss": 3, "pvoigt": 4, "xrd": 9}[spec.peak_kind]
+    if j < K * npk:
+        pk = getattr(spec, "peak_prior_k", None)
+        return (pk[j // npk] if pk is not None else spec.peak_prior)[j % npk]
+    return spec.bg_prior[j - K * npk]
+
+
+@pytest.mark.parametrize("make,K,M,n", [(lambda: W.pvoigt5_n1001(0), 5, 4096, 16),
+                                        (lambda: W.pvoigt5_n1001(0), 2, 1001, 3),
+                                        (lambda: W.gauss3_n201(0), 4, 2, 10),
+                                        (lambda: W.linear_gaussian(), 2, 777, 8)])
+def test_step_sizes_match_reference(orc, make, K, M, n):
+    """The stage's step-size kernels on identical inputs against the reference's
+    or_update_lambda / or_step_sizes: lambda_j <- clamp(lambda_j exp(acc_j/(M n) - 0.44),
+    0.01, 10), then s_j = lambda_j sd_j over the resampled states (FP64 on both sides; the
+    GPU rounds s_j to FP32 once).  Includes multipliers driven into both clamps; components
+    with a FIXED prior keep lambda and get step 0."""
+    torch = torch_cuda()
+    spec = make()
+    pr = native.Problem(spec, K, K)
+    d = pr.dim(K)
+    rng = np.random.default_rng(1000 * K + M)
+    start = (rng.normal(size=(M, d)) * rng.uniform(0.01, 3.0, d) + rng.uniform(-5, 5, d)).astype(np.float32)
+    if M > 2:
+        start[:, 0] = start[0, 0]          # a constant column: the SD floor
+    lam = rng.uniform(0.05, 5.0, d)
+    acc = rng.integers(0, M * n + 1, d).astype(np.int32)
+    lam[-1], acc[-1] = 9.9, M * n           # pushed over 10
+    if d > 2:
+        lam[1], acc[1] = 0.0101, 0          # pushed under 0.01
+    fixed = np.array([_component_prior(spec, K, j)[0] == "fixed" for j in range(d)])
+    acc[fixed] = 0
+    say("step sizes", spec.n, K, M, n, "fixed", int(fixed.sum()))
+    d_lam = dev(lam, torch.float64)
+    d_acc = dev(acc, torch.int32)
+    d_step = torch.zeros(d, dtype=torch.float32, device="cuda")
+    native.smc_kernel_step_sizes(pr, K, dev(start.T.copy(), torch.float32), M, n, d_lam, d_acc, d_step)
+    lam_gpu, step_gpu = d_lam.cpu().numpy(), d_step.cpu().numpy().astype(np.float64)
+    assert np.all(d_acc.cpu().numpy() == 0)
+    lam_ref = orc.update_lambda(lam, acc, float(M * n))
+    free = ~fixed
+    assert np.allclose(lam_gpu[free], lam_ref[free], rtol=1e-14, atol=0), (lam_gpu, lam_ref)
+    assert np.array_equal(lam_gpu[fixed], lam[fixed])
+    assert lam_gpu[-1] == 10.0 or fixed[-1]
+    if d > 2 and not fixed[1]:
+        assert lam_gpu[1] == 0.01
+    step_ref = orc.step_sizes(start.astype(np.float64), lam_ref)
+    assert np.allclose(step_gpu[free], step_ref[free], rtol=1.2e-7, atol=0), (step_gpu, step_ref)
+    assert np.all(step_gpu[fixed] == 0.0)

@@ -4,10 +4,8 @@ FP64 reference, through the C ABI.
 Stage 0 draws from the priors (tables spectral_priors etc.); the move is the
 component-wise random-walk MH of Sec. II.B.4 (standard and waste-free,
 Sec. II.B.3); the whole sampler estimates log Z = -F(K) (Eqs.
-smc_marginal_likelihood, free_energy_def).  log Z is a random estimate, so the
-end-to-end bar is statistical: over 10 seeds the mean difference to the
-reference is within 3 Monte Carlo standard errors and 0.05 nats, with the same
-argmax K.
+smc_marginal_likelihood, free_energy_def), checked here against closed forms;
+the end-to-end parity with the reference over 10 seeds is in test_gpu_evidence.py.
 """
 import math
 
@@ -15,7 +13,6 @@ import numpy as np
 import pytest
 from scipy import stats
 
-import oracle_runs
 from gpu_util import delta_ok, dev, energy_constant, f32, say, torch_cuda
 from paper_2604_03271_amd import native, workloads as W
 
@@ -141,14 +138,6 @@ def _gpu_logz(spec, seed, **kw):
     return out
 
 
-def _stat_parity(g, o, tol=0.05):
-    """Per-K: |mean diff| <= 3 combined SE and <= tol."""
-    g, o = np.asarray(g), np.asarray(o)
-    d = g.mean(0) - o.mean(0)
-    se = np.sqrt(g.var(0, ddof=1) / len(g) + o.var(0, ddof=1) / len(o))
-    return d, se
-
-
 def test_linear_gaussian_closed_form():
     from test_oracle_sampler import lin_gauss_logz
     sp = W.linear_gaussian()
@@ -167,39 +156,6 @@ def test_k1_quadrature():
     lz = np.array([_gpu_logz(sp, s, n_particles=8192, n_moves=16, waste_free=True)[0] for s in range(1, 11)])
     se = lz.std(ddof=1) / math.sqrt(len(lz))
     assert abs(lz.mean() - exact) <= 3 * se + 0.03, (lz.mean(), exact, se)
-
-
-def test_gauss3_n201_parity_with_reference(orc):
-    """Three Gaussian peaks (N=201, K=1..4, standard mode, n=10), 10 seeds on both sides."""
-    spec = W.gauss3_n201(0)
-    P = 2048
-    g = []
-    for seed in range(1, 11):
-        say("e2e gauss3_n201 seed", seed)
-        g.append(_gpu_logz(spec, seed, n_particles=P, n_moves=10, waste_free=False))
-    o = oracle_runs.log_evidence(orc, "gauss3_n201", say)
-    d, se = _stat_parity(g, o)
-    say("gauss3_n201 diff", d, "se", se, "gpu", np.mean(g, 0), "ref", np.mean(o, 0))
-    assert np.all(np.abs(d) <= 3 * se + 1e-9) and np.all(np.abs(d) <= 0.05 + 3 * se), (d, se)
-    assert np.argmax(np.mean(g, 0)) == np.argmax(np.mean(o, 0))
-
-
-def test_pvoigt5_n1001_parity_with_reference(orc):
-    """Five pseudo-Voigt peaks (N=1001, pseudo-Voigt + linear background, waste-free n=16) at a reduced
-    P = 4096 and K = 4..5 (clearly separated evidences), 10 seeds on both sides.  (The N=4096 Poisson pattern's
-    reference run takes minutes per K even at P = 512; its stage is checked at full size.)"""
-    spec = W.pvoigt5_n1001(0)
-    spec.k_min, spec.k_max = 4, 5
-    P = 4096
-    g = []
-    for seed in range(1, 11):
-        say("e2e pvoigt5_n1001 seed", seed)
-        g.append(_gpu_logz(spec, seed, n_particles=P, n_moves=16, waste_free=True))
-    o = oracle_runs.log_evidence(orc, "pvoigt5_n1001", say)
-    d, se = _stat_parity(g, o)
-    say("pvoigt5_n1001 diff", d, "se", se, "gpu", np.mean(g, 0), "ref", np.mean(o, 0))
-    assert np.all(np.abs(d) <= 3 * se + 1e-9) and np.all(np.abs(d) <= 0.05 + 3 * se), (d, se)
-    assert np.argmax(np.mean(g, 0)) == np.argmax(np.mean(o, 0))
 
 
 def test_sampler_trace_invariants():
@@ -301,15 +257,14 @@ def test_evaluation_kinds():
 def test_tuner_picks_a_supported_lane_count(make, allowed):
     """The autotuner returns a lane count that holds the problem, caches it, and a run with it
     gives finite evidences."""
-    import time
     spec = make()
     opt = native.options(seed=1, n_particles=8192, n_moves=8, waste_free=True)
     say("tune", spec.n)
     lanes, ns = native.smc_tune_lanes(native.Problem(spec), opt, stages=2)
     assert lanes in allowed and 0 < ns < 1e3, (lanes, ns)
-    t0 = time.perf_counter()
-    assert native.smc_tune_lanes(native.Problem(spec), opt, stages=2) == (lanes, ns)   # cached
-    assert time.perf_counter() - t0 < 0.05
+    # cached: the second call returns the first call's measured time itself (a new
+    # measurement would not repeat a timing to every bit)
+    assert native.smc_tune_lanes(native.Problem(spec), opt, stages=2) == (lanes, ns)
     s = native.Sampler(spec, native.options(seed=1, n_particles=8192, n_moves=8, waste_free=True, lanes_per_chain=lanes))
     for _ in range(3):
         s.step()

@@ -1,8 +1,9 @@
 """Pins of the reference's random streams and prior laws (CPU only).
 
 Philox4x32-10 (Salmon et al., SC'11) is a keyed bijection of 128-bit counters;
-its exact output is pinned against rocRAND's own generator in
-tests/test_gpu_philox.py (that library needs the HIP runtime).  Here: the
+its exact output is pinned against rocRAND's own generator by
+test_philox_reference_matches_rocrand in tests/test_gpu_kernels.py (that
+library needs the HIP runtime).  Here: the
 statistical properties of the stream, and the prior draws and densities of the
 paper's prior tables (spectral_priors, xrd_priors, xps_priors) against scipy.
 """
