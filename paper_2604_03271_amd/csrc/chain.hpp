@@ -13,17 +13,19 @@
 // (one peak, or the background), so every lane keeps, per point,
 //   D = y - (model without the current term)   (Gaussian noise)
 //   D = model without the current term          (Poisson counts)
-// and the current peak's basis shapes at every point, t = x - mu: e = exp(-(b/2) t^2)
-// for a Gaussian peak (value A e); e = exp(-ln2 t^2 / s^2) and l = 1 / (s^2 + t^2)
-// for a pseudo-Voigt peak (value A eta e + A (1 - eta) s^2 l).  The background
-// c0 + c1 x needs no cache.  Each term is linear in its remaining parameters, so a
-// proposal of a
-// centre or width re-evaluates the shapes (the transcendental work); a proposal
-// of an amplitude, a Gaussian fraction or a background coefficient only forms
-// the residual from the cached shapes.  Moving to the next term costs one
+// and the current peak's basis shapes at every point, t = x - mu: e = 2^(c t^2)
+// for a Gaussian peak (value A e); e = 2^(-u) and l = 1/u with u = 1 + t^2/s^2 for a
+// pseudo-Voigt peak (value 2 A eta e + A (1 - eta) l, which is
+// A [eta e^(-ln2 t^2/s^2) + (1 - eta) s^2/(s^2 + t^2)]).  The background c0 + c1 x
+// needs no cache.  Each term is linear in its remaining parameters, so a proposal
+// of a centre or width re-evaluates the shapes (the transcendental work); a
+// proposal of an amplitude, a Gaussian fraction or a background coefficient only
+// forms the residual from the cached shapes.  Moving to the next term costs one
 // shape evaluation.  D and the shapes are rebuilt from scratch every few
 // sweeps, so rounding cannot accumulate.
 #pragma once
+
+#include <type_traits>
 
 #include "smc_device.hpp"
 
@@ -45,8 +47,18 @@ constexpr int kRebuildEvery = 8;
 // Component q of a peak enters its term linearly: amplitude (both kinds) and
 // Gaussian fraction (pseudo-Voigt).
 template <int PK>
-__device__ __forceinline__ bool linear_component(int q) {
+__host__ __device__ constexpr bool linear_component(int q) {
     return q == 0 || (PK == SMC_PEAK_PVOIGT && q == 3);
+}
+
+// A decision that every lane of a chain takes alike (its inputs have the same bits in all
+// of them).  When a chain fills whole wavefronts the ballot of the active lanes is the
+// decision of the wavefront, in scalar registers, so the branch on it is a scalar branch
+// and what it guards needs no lane masks.
+template <int L>
+__device__ __forceinline__ bool chain_uniform(bool c) {
+    if constexpr (L == 64) return __builtin_amdgcn_ballot_w64(c) != 0;
+    else return c;
 }
 
 template <int PK, int NZ, int L, int WPC, int PPL>
@@ -77,11 +89,7 @@ struct ChainState {
 
     // Unit shapes of a peak at point p.
     __device__ __forceinline__ void shape_at(const PeakC& q, int p, float& e, float& l) const {
-        const float t = x[p] - q.mu;
-        const float t2 = t * t;
-        e = __builtin_amdgcn_exp2f(q.c * t2);
-        if constexpr (kPV) l = __builtin_amdgcn_rcpf(q.s2 + t2);
-        else l = 0.0f;
+        peak_shapes<PK>(q, x[p] - q.mu, e, l);
     }
 
     __device__ __forceinline__ float s2(int p) const {
@@ -299,8 +307,8 @@ __global__ void __launch_bounds__(256) k_energy(const GroupDesc* __restrict__ gr
 // Chain m starts from start[.][m]; standard mode writes its state after the
 // last sweep to particle m, waste-free mode writes the state after sweep t to
 // particle m * n + t (Sec. II.B.3).
-// LDS: the prior table [d]; per chain slot theta[d], increment s_j z_j [d], ln u_j [d];
-// then the per-component accept counters [d] and the cross-wave reduction buffer.
+// LDS: the prior table [d]; per chain slot theta[d], increment s_j z_j [d], ln u_j [d] and
+// the chain's accept counters [d]; then the cross-wave reduction buffer.
 
 template <int PK, int NZ, int L, int WPC, int PPL>
 __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(const GroupDesc* __restrict__ groups,
@@ -308,6 +316,7 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(
     using CS = ChainState<PK, NZ, L, WPC, PPL>;
     constexpr int LC = CS::LC;
     constexpr int CPW = 256 / LC;
+    constexpr int NP = PK == SMC_PEAK_GAUSS ? 3 : 4;   // parameters of one peak
     const MoveWork w = work[xcd_block(blockIdx.x, gridDim.x, LC / 16)];
     const GroupDesc& g = groups[w.group];
     GroupState* st = g.st;
@@ -316,18 +325,22 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(
     if (d == 0) return;
 
     extern __shared__ float lds[];
-    const int slot = threadIdx.x / LC, lane = threadIdx.x % LC;
+    // a chain of whole wavefronts: its slot is the same in every lane (a scalar), so the
+    // chain's addresses and control flow are scalar too
+    const int slot = L == 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / LC) : threadIdx.x / LC;
+    const int lane = threadIdx.x % LC;
     DevPrior* pri = reinterpret_cast<DevPrior*>(lds);   // [d], read once per proposal
     float* body = lds + 4 * d;
-    float* th = body + slot * 3 * d;
+    float* th = body + slot * 4 * d;
     float* inc = th + d;
     float* lnu = inc + d;
-    uint32_t* accc = reinterpret_cast<uint32_t*>(body + CPW * 3 * d);
-    float* red = body + CPW * 3 * d + d;
+    uint32_t* accs = reinterpret_cast<uint32_t*>(lnu + d);   // this chain's accepted proposals [d]
+    uint32_t* acc0 = reinterpret_cast<uint32_t*>(body + 3 * d);   // the first slot's
+    float* red = body + CPW * 4 * d;
     uint32_t* nevals = reinterpret_cast<uint32_t*>(red + 2 * WPC);   // [0] shape, [1] linear
     // the proposal's shapes, [chain slot][point][lane], 8-byte aligned after the above
     constexpr int kSB = move_shape_lds_bytes(PK, NZ, PPL, LC);
-    float* shp = lds + ((4 * d + CPW * 3 * d + d + 2 * WPC + 2 + 1) & ~1);
+    float* shp = lds + ((4 * d + CPW * 4 * d + 2 * WPC + 2 + 1) & ~1);
     float* my_shp = shp + (kSB / 4) * (slot * PPL * LC + lane);
 
     const bool active = slot < w.nchains;
@@ -337,10 +350,8 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(
     const uint32_t stage = static_cast<uint32_t>(st->stage);
     const uint32_t K = static_cast<uint32_t>(g.K);
 
-    for (int j = threadIdx.x; j < d; j += 256) {
-        accc[j] = 0u;
-        pri[j] = g.prior[j];
-    }
+    for (int j = threadIdx.x; j < d; j += 256) pri[j] = g.prior[j];
+    for (int j = threadIdx.x; j < CPW * d; j += 256) reinterpret_cast<uint32_t*>(body)[(j / d) * 4 * d + 3 * d + j % d] = 0u;
     if (threadIdx.x < 2) nevals[threadIdx.x] = 0u;
     uint32_t my_shape = 0, my_linear = 0;
     float E = 0.0f;
@@ -352,6 +363,73 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(
     if (active) cs.load_points(g, lane);
     const int kt = g.K + (g.nbg > 0 ? 1 : 0);
     int parity = 0;
+
+    // One Metropolis-Hastings proposal of component j = j0 + q of the current term (peak or
+    // background) whose constants are qc, from the state tk = th + j0 of that term.  Q >= 0:
+    // a peak component known at compile time (the constants are updated field by field);
+    // Q == kBgComp: a background coefficient; Q == kAnyComp: a peak component known at run time
+    // (chains narrower than a wavefront, whose code size and registers the unrolled form
+    // would raise).  An accept updates E, qc, the cached shapes and the state.
+    constexpr int kBgComp = -1, kAnyComp = -2;
+    bool any_bg = false;
+    int nq_any = 0;
+    auto propose = [&](auto qtag, int j0, int q, float* tk, PeakC& qc) {
+        constexpr int Q = decltype(qtag)::value;
+        constexpr bool kBg = Q == kBgComp;
+        constexpr bool kAny = Q == kAnyComp;
+        const int qi = Q < 0 ? q : Q;
+        const int j = j0 + qi;
+        const DevPrior pr = pri[j];
+        if (pr.kind == SMC_PRIOR_FIXED) return;
+        const float vo = tk[qi];
+        const float vn = vo + inc[j];
+        if (!chain_uniform<L>(prior_in_support(pr, vn))) return;
+        PeakC qn;
+        if constexpr (kBg) {
+            qn = qc;
+            if (qi == 0) qn.aG = vn;
+            else qn.aL = vn;
+        } else if constexpr (kAny) {
+            float tmp[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) tmp[u] = (u < nq_any) ? tk[u] : 0.0f;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (u == qi) tmp[u] = vn;
+            qn = any_bg ? bg_consts(tmp, g.nbg) : peak_consts<PK>(tmp);
+        } else {
+            qn = peak_consts_with<PK, (Q < 0 ? 0 : Q)>(qc, tk, vn);
+        }
+        const bool linear = kBg || (kAny && any_bg) || linear_component<PK>(qi);
+        float part;
+        if (kBg || (kAny && any_bg)) {
+            part = cs.partial_bg(qn);
+        } else if (linear) {
+            part = cs.partial_linear(qn);
+        } else {
+            if constexpr (kSB > 0) part = cs.partial_shape_store(qn, my_shp);
+            else part = cs.partial_shape(qn);
+        }
+        if (linear) ++my_linear;
+        else ++my_shape;
+        float En = chain_sum<L, WPC>(part, red, parity);
+        if (NZ == SMC_NOISE_GAUSS) En *= g.inv2s2;
+        const float log_alpha = -beta * (En - E) + prior_log_ratio(pr, vn, vo);
+        if (chain_uniform<L>(lnu[j] < log_alpha)) {
+            E = En;
+            if constexpr (!kAny) qc = qn;   // (kAny: the caller forms the constants again)
+            if (!linear) {
+                if constexpr (kSB > 0) cs.load_shapes(my_shp);
+                else cs.accept_shape(qn);
+            }
+            tk[qi] = vn;
+            if constexpr (L == 64) {
+                if (lane == 0) ++accs[j];   // this chain's own counter: one lane writes it
+            } else if (lane == 0) {
+                atomicAdd(&acc0[j], 1u);    // chains sharing a wavefront share the first slot's counters
+            }
+        }
+    };
 
     for (int t = 0; t < n; ++t) {
         __syncthreads();
@@ -370,52 +448,34 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(
             } else if (kt > 1) {
                 cs.transition(g, th, kt - 1, 0);
             }
-            for (int k = 0; k < kt; ++k) {
-                const bool is_bg = k == g.K;
-                const int j0 = is_bg ? g.K * g.np : k * g.np;
-                const int nq = is_bg ? g.nbg : g.np;
-                if (k > 0) cs.transition(g, th, k - 1, k);
-                for (int q = 0; q < nq; ++q) {
-                    const int j = j0 + q;
-                    const DevPrior pr = pri[j];
-                    if (pr.kind == SMC_PRIOR_FIXED) continue;
-                    const float vo = th[j];
-                    const float vn = vo + inc[j];
-                    if (!prior_in_support(pr, vn)) continue;
-                    // constants of the term with component j replaced
-                    float tmp[4];
-                    const float* base = th + j0;
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) tmp[u] = (u < nq) ? base[u] : 0.0f;
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        if (u == q) tmp[u] = vn;
-                    const PeakC qn = is_bg ? bg_consts(tmp, g.nbg) : peak_consts<PK>(tmp);
-                    const bool linear = is_bg || linear_component<PK>(q);
-                    float part;
-                    if (is_bg) {
-                        part = cs.partial_bg(qn);
-                    } else if (linear) {
-                        part = cs.partial_linear(qn);
-                    } else if constexpr (kSB > 0) {
-                        part = cs.partial_shape_store(qn, my_shp);
-                    } else {
-                        part = cs.partial_shape(qn);
-                    }
-                    if (linear) ++my_linear;
-                    else ++my_shape;
-                    float En = chain_sum<L, WPC>(part, red, parity);
-                    if (NZ == SMC_NOISE_GAUSS) En *= g.inv2s2;
-                    const float log_alpha = -beta * (En - E) + prior_log_ratio(pr, vn, vo);
-                    if (lnu[j] < log_alpha) {
-                        E = En;
-                        if (!linear) {
-                            if constexpr (kSB > 0) cs.load_shapes(my_shp);
-                            else cs.accept_shape(qn);
-                        }
-                        th[j] = vn;
-                        if (lane == 0) atomicAdd(&accc[j], 1u);
-                    }
+            if constexpr (L == 64) {
+            // the peaks, components in order (Sec. II.B.4); the current term's constants are
+            // kept in qc and its shapes in the cache
+            for (int k = 0; k < g.K; ++k) {
+                float* tk = th + k * NP;
+                PeakC qc = peak_consts<PK>(tk);
+                if (k > 0) cs.exclude(false, qc);
+                propose(std::integral_constant<int, 0>{}, k * NP, 0, tk, qc);
+                propose(std::integral_constant<int, 1>{}, k * NP, 1, tk, qc);
+                propose(std::integral_constant<int, 2>{}, k * NP, 2, tk, qc);
+                if constexpr (NP > 3) propose(std::integral_constant<int, 3>{}, k * NP, 3, tk, qc);
+                if (k + 1 < kt) cs.include(false, qc, true);
+            }
+            // the background coefficients
+            if (g.nbg > 0) {
+                float* tb = th + g.K * NP;
+                PeakC qb = bg_consts(tb, g.nbg);
+                cs.exclude(true, qb);
+                for (int q = 0; q < g.nbg; ++q) propose(std::integral_constant<int, kBgComp>{}, g.K * NP, q, tb, qb);
+            }
+            } else {
+                PeakC unused{};
+                for (int k = 0; k < kt; ++k) {
+                    any_bg = k == g.K;
+                    const int j0 = k * NP;
+                    nq_any = any_bg ? g.nbg : NP;
+                    if (k > 0) cs.transition(g, th, k - 1, k);
+                    for (int q = 0; q < nq_any; ++q) propose(std::integral_constant<int, kAnyComp>{}, j0, q, th + j0, unused);
                 }
             }
             const size_t out = g.waste_free ? (size_t)m * n + t : (size_t)m;
@@ -430,8 +490,11 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(
         if (my_linear) atomicAdd(&nevals[1], my_linear);
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < d; j += 256)
-        if (accc[j]) atomicAdd(&g.acc[j], accc[j]);
+    for (int j = threadIdx.x; j < d; j += 256) {
+        uint32_t a = 0;
+        for (int c = 0; c < CPW; ++c) a += reinterpret_cast<const uint32_t*>(body)[c * 4 * d + 3 * d + j];
+        if (a) atomicAdd(&g.acc[j], a);
+    }
     if (threadIdx.x == 0 && (nevals[0] | nevals[1])) {
         atomicAdd(&g.st->evals, static_cast<unsigned long long>(nevals[0]) + nevals[1]);
         if (nevals[1]) atomicAdd(&g.st->evals_linear, static_cast<unsigned long long>(nevals[1]));

@@ -86,10 +86,7 @@ struct XpsChain {
     }
 
     __device__ __forceinline__ void shape_at(const PeakC& q, int p, float& e, float& l) const {
-        const float t = x[p] - q.mu;
-        const float t2 = t * t;
-        e = __builtin_amdgcn_exp2f(q.c * t2);
-        l = __builtin_amdgcn_rcpf(q.s2 + t2);
+        peak_shapes<SMC_PEAK_PVOIGT>(q, x[p] - q.mu, e, l);
     }
 
     __device__ __forceinline__ static float value(const PeakC& q, float e, float l) {

@@ -107,36 +107,78 @@ __device__ __forceinline__ float prior_log_ratio(const DevPrior& pr, float vn, f
 
 // ---------------------------------------------------------------------------
 // Peak profiles.  A peak's per-particle constants are hoisted out of the point
-// loop:
-//   Gaussian  A exp(-(b/2) t^2)        = A * 2^(cb t^2),        cb = -(b/2) log2 e
-//   pseudo-Voigt A[eta e^{-ln2 t^2/s^2} + (1-eta) s^2/(s^2+t^2)]
-//                                      = aG 2^(cg t^2) + aL / (s2 + t^2),
-//             cg = -1/s^2, s2 = s^2, aG = A eta, aL = A (1-eta) s^2
-//   background c0 + c1 x  (constant background: c1 = 0)
-// with t = x - mu evaluated exactly near the peak (Sterbenz).
+// loop (t = x - mu, evaluated exactly near the peak by Sterbenz's lemma):
+//   Gaussian      A exp(-(b/2) t^2)                        = aG 2^(c t^2),
+//                 c = -(b/2) log2 e, aG = A
+//   pseudo-Voigt  A [eta e^(-ln2 t^2/s^2) + (1-eta) s^2/(s^2+t^2)] = aG 2^(-u) + aL / u,
+//                 u = 1 + c t^2, c = 1/s^2, aG = 2 A eta, aL = A (1 - eta)
+// (one fma forms u, which serves both shapes: 2^(-t^2/s^2) = 2 * 2^(-u) and
+// s^2/(s^2 + t^2) = 1/u); background c0 + c1 x (constant background: c1 = 0).
 // ---------------------------------------------------------------------------
 struct PeakC {
-    float mu, c, s2, aG, aL;
+    float mu, c, aG, aL;
 };
 
 template <int PK>
 __device__ __forceinline__ PeakC peak_consts(const float* th) {
     PeakC q;
+    q.mu = th[1];
     if constexpr (PK == SMC_PEAK_GAUSS) {
-        q.mu = th[1];
         q.c = -0.5f * kLog2e * th[2];
-        q.s2 = 0.0f;
         q.aG = th[0];
         q.aL = 0.0f;
     } else {
-        const float s = th[2];
-        q.mu = th[1];
-        q.s2 = s * s;
-        q.c = -__builtin_amdgcn_rcpf(q.s2);   // v_rcp (1 ulp): no IEEE division sequence per proposal
-        q.aG = th[0] * th[3];
-        q.aL = th[0] * (1.0f - th[3]) * q.s2;
+        q.c = __builtin_amdgcn_rcpf(th[2] * th[2]);   // v_rcp (1 ulp): no IEEE division sequence per proposal
+        q.aG = 2.0f * (th[0] * th[3]);
+        q.aL = th[0] * (1.0f - th[3]);
     }
     return q;
+}
+
+// The constants of peak th with component Q replaced by v, from the constants qc of th itself:
+// only the fields that depend on component Q are formed, each by the expression of
+// peak_consts, so the result has the bits of peak_consts of the modified vector.
+template <int PK, int Q>
+__device__ __forceinline__ PeakC peak_consts_with(const PeakC& qc, const float* th, float v) {
+    PeakC q = qc;
+    if constexpr (Q == 1) {
+        q.mu = v;
+    } else if constexpr (PK == SMC_PEAK_GAUSS) {
+        if constexpr (Q == 0) q.aG = v;
+        else q.c = -0.5f * kLog2e * v;
+    } else if constexpr (Q == 0) {
+        q.aG = 2.0f * (v * th[3]);
+        q.aL = v * (1.0f - th[3]);
+    } else if constexpr (Q == 2) {
+        q.c = __builtin_amdgcn_rcpf(v * v);
+    } else {
+        q.aG = 2.0f * (th[0] * v);
+        q.aL = th[0] * (1.0f - v);
+    }
+    return q;
+}
+
+// Unit shapes of a peak at distance t from its centre: e (the exponential, in the
+// units of aG) and, for a pseudo-Voigt peak, l (the Lorentzian, in the units of aL).
+template <int PK>
+__device__ __forceinline__ void peak_shapes(const PeakC& q, float t, float& e, float& l) {
+    const float t2 = t * t;
+    if constexpr (PK == SMC_PEAK_GAUSS) {
+        e = __builtin_amdgcn_exp2f(q.c * t2);
+        l = 0.0f;
+    } else {
+        const float u = __builtin_fmaf(t2, q.c, 1.0f);
+        e = __builtin_amdgcn_exp2f(-u);
+        l = __builtin_amdgcn_rcpf(u);
+    }
+}
+
+template <int PK>
+__device__ __forceinline__ float peak_eval(float x, const PeakC& q) {
+    float e, l;
+    peak_shapes<PK>(q, x - q.mu, e, l);
+    if constexpr (PK == SMC_PEAK_GAUSS) return q.aG * e;
+    else return __builtin_fmaf(q.aL, l, q.aG * e);
 }
 
 __device__ __forceinline__ PeakC bg_consts(const float* th, int nbg) {
@@ -144,17 +186,6 @@ __device__ __forceinline__ PeakC bg_consts(const float* th, int nbg) {
     q.aG = nbg > 0 ? th[0] : 0.0f;
     q.aL = nbg > 1 ? th[1] : 0.0f;
     return q;
-}
-
-template <int PK>
-__device__ __forceinline__ float peak_eval(float x, const PeakC& q) {
-    const float t = x - q.mu;
-    const float t2 = t * t;
-    if constexpr (PK == SMC_PEAK_GAUSS) {
-        return q.aG * __builtin_amdgcn_exp2f(q.c * t2);
-    } else {
-        return __builtin_fmaf(q.aL, __builtin_amdgcn_rcpf(q.s2 + t2), q.aG * __builtin_amdgcn_exp2f(q.c * t2));
-    }
 }
 
 __device__ __forceinline__ float bg_eval(float x, const PeakC& q) { return __builtin_fmaf(q.aL, x, q.aG); }

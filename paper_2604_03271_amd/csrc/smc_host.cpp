@@ -230,7 +230,7 @@ static size_t reduce_floats(const Tile& t) { return 2 * static_cast<size_t>(t.la
 
 size_t move_lds_bytes(const Tile& t, int d, int peak_kind, int noise_kind) {
     const int cpw = tile_chains_per_wg(t);
-    size_t b = sizeof(DevPrior) * d + sizeof(float) * (static_cast<size_t>(cpw) * 3 * d + d + reduce_floats(t));
+    size_t b = sizeof(DevPrior) * d + sizeof(float) * (static_cast<size_t>(cpw) * 4 * d + reduce_floats(t));
     const int sb = move_shape_lds_bytes(peak_kind, noise_kind, t.ppl, t.lanes);
     if (sb > 0) b = ((b + 7) & ~static_cast<size_t>(7)) + static_cast<size_t>(sb) * tile_threads(t) * t.ppl;
     return b;
