@@ -303,6 +303,19 @@ smc_status smc_kernel_ess_bisect(const float* energy, int32_t P, double beta, do
 smc_status smc_kernel_resample(const double* weights, int32_t P, int32_t M, uint32_t r, int32_t* ancestors,
                                void* stream);
 
+/* For callers that cannot allocate device memory (code under stream capture, serving loops
+ * and harnesses that forbid hipMalloc): smc_kernel_resample with the same kernels and the same
+ * ancestors, whose scratch (descriptor, group state, integer CDF [P], chunk scratch) is a
+ * static device array of the library, about 8.5 MB per GPU, held until the process ends, so
+ * it calls no hipMalloc / hipFree.  P is limited to SMC_NOALLOC_MAX_P (SMC_EINVAL beyond).
+ * Asynchronous: the work is queued on `stream` (NULL = the null stream) and the call
+ * returns without waiting; ancestors (device) [M] are valid once that work completes.  Every
+ * call on one GPU shares that GPU's array, so calls whose work overlaps on one GPU (other
+ * streams, other host threads) race; calls queued on one stream are ordered. */
+#define SMC_NOALLOC_MAX_P (1 << 20)
+smc_status smc_kernel_resample_noalloc(const double* weights, int32_t P, int32_t M, uint32_t r,
+                                       int32_t* ancestors, void* stream);
+
 /* Posterior summary kernels on caller buffers: theta (device) [d][P] FP32 component-major,
  * optional relabelling of n_peaks peaks of np parameters (centre at offset 1; 0 = none),
  * outputs as for smc_posterior_summary (host).  The device scratch (d*P floats when

@@ -20,7 +20,7 @@ FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-I" + os.path.j
          "-Wall", "-Wno-unused-function", "-Wno-pass-failed"]
 SOURCES = ["kernels_00.hip", "kernels_01.hip", "kernels_10.hip", "kernels_11.hip", "kernels_xps.hip", "kernels_xrd.hip",
            "stage.hip",
-           "summary.hip", "smc_host.cpp", "hooks.cpp", "batch.cpp"]
+           "summary.hip", "smc_host.cpp", "hooks.cpp", "batch.cpp", "noalloc.cpp"]
 
 
 def _compile(src, verbose):

@@ -123,6 +123,7 @@ _SIGNATURES = {
     "smc_kernel_move": (c_i32, [P(smc_problem), c_i32, c_vp, c_vp, c_i32, c_i32, c_i32, c_d, c_u64, c_u32,
                                 c_vp, c_vp, c_vp, c_vp, c_i32, c_vp]),
     "smc_kernel_step_sizes": (c_i32, [P(smc_problem), c_i32, c_vp, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp]),
+    "smc_kernel_resample_noalloc": (c_i32, [c_vp, c_i32, c_i32, c_u32, c_vp, c_vp]),
 }
 
 
@@ -496,6 +497,12 @@ def smc_kernel_ess_bisect(energy, beta: float, rho: float = 0.5, iters: int = 50
 def smc_kernel_resample(weights, M: int, r: int, ancestors, stream=None) -> None:
     check(lib().smc_kernel_resample(_ptr(weights), weights.numel(), M, r, _ptr(ancestors), _stream_ptr(stream)),
           "smc_kernel_resample")
+
+
+def smc_kernel_resample_noalloc(weights, M: int, r: int, ancestors, stream=None) -> None:
+    """As smc_kernel_resample, without device allocation; asynchronous on the stream."""
+    check(lib().smc_kernel_resample_noalloc(_ptr(weights), weights.numel(), M, r, _ptr(ancestors),
+                                            _stream_ptr(stream)), "smc_kernel_resample_noalloc")
 
 
 def smc_kernel_summary(theta, d: int, P: int, probs, n_peaks: int = 0, np_: int = 3, stream=None):
