@@ -35,23 +35,35 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work per particle*point of the move kernel, Gaussian noise.  A proposal of
-# a peak's centre or width re-evaluates its basis shapes at every point:
-#   pseudo-Voigt: t = x - mu, t^2, c t^2, s^2 + t^2, two fmas for the residual, one fma
-#   for r^2 -> 7 VALU, plus exp2 and rcp -> 2 transcendental;
-#   Gaussian peak: t, t^2, c t^2, one fma for the residual, one for r^2 -> 5 VALU + exp2.
-# A proposal of a linear coefficient (amplitude, Gaussian fraction, background) forms the
-# residual from cached shapes: counted as 2 VALU (one fma for the residual, one for r^2),
-# a lower bound.
-SHAPE_VALU = {"pvoigt": 7, "gauss": 5}
+# Algorithmic work of the move kernel per particle*point, in FP32 VALU issue slots: the
+# fewest instructions the incremental method needs (residual cache D = y - the model without
+# the current term, the current peak's basis shapes cached), Gaussian noise.
+#   A proposal of a peak's centre or width re-evaluates its shapes at every point:
+#     pseudo-Voigt: t = x - mu, t^2, u = 1 + c t^2 (fma), 2^-u, 1/u (the two shapes share u),
+#     two fmas for the residual, one fma for r^2 -> 6 VALU + 2 transcendental;
+#     Gaussian peak: t, t^2, c t^2, 2^(.), one fma for the residual, one for r^2 -> 5 + 1.
+#   A proposal of a linear coefficient forms the residual from the cached shapes: one fma per
+#   basis function of the term (pseudo-Voigt 2: A eta e and A (1 - eta) l; Gaussian 1) and
+#   one fma for r^2 (a background coefficient of a pseudo-Voigt model: its value c0 + c1 x,
+#   the residual and r^2, also 3).
+#   The term switch: in one sweep every term becomes the current one once.  A peak then has
+#   its shapes evaluated at the current state (pseudo-Voigt 3 VALU + 2 transcendental,
+#   Gaussian 3 + 1), its value taken out of D and, when the next term takes over, put back
+#   (2 x 2 fma pseudo-Voigt, 2 x 1 Gaussian): 9 and 6 slots per point; a background of nb
+#   coefficients 2 nb (its value and the update, out and back).  These are per chain and
+#   sweep, whatever the proposals do.
+SHAPE_VALU = {"pvoigt": 6, "gauss": 5}
 SHAPE_TRANS = {"pvoigt": 2, "gauss": 1}
-LINEAR_VALU = 2
-# Poisson counts (N=4096, 16 pseudo-Voigt peaks): the point term needs f (the fma that adds the term's value to the
-# rest of the model), ln f and y ln f subtracted and summed (fma, add): a shape proposal is the
-# profile's shape work (pseudo-Voigt 4 VALU + exp2, rcp; Gaussian 3 + exp2), 2 or 1 fma for the
-# value, then 2 VALU + log; a linear proposal 3 VALU + log.
-SHAPE_POISSON = {"pvoigt": (8, 3), "gauss": (6, 2)}
-LINEAR_POISSON = (3, 1)
+LINEAR_VALU = {"pvoigt": 3, "gauss": 2}
+SWITCH_PEAK = {"pvoigt": (7, 2), "gauss": (5, 1)}
+SWITCH_BG_PER_COEFF = 2
+# Poisson counts (N=4096, 16 pseudo-Voigt peaks): the point term is f h((y-f)/f) = f - y ln f
+# up to the data's constant, from f = D + the term's value: ln f, the fma with -y and the
+# sum (2 VALU + log); a shape proposal adds the profile's shapes and its value (pseudo-Voigt
+# 3 + 2 fma + 2 transcendental; Gaussian 3 + 1 fma + 1), a linear proposal its value
+# from the cached shapes (2 or 1 fma).  The switch as for Gaussian noise.
+SHAPE_POISSON = {"pvoigt": (7, 3), "gauss": (6, 2)}
+LINEAR_POISSON = {"pvoigt": (4, 1), "gauss": (3, 1)}
 # XPS model form (Shirley background, heteroscedastic noise), per point: a centre/width
 # proposal forms the new shapes (4 VALU + exp2, rcp), the new value (2), the change (1),
 # its trapezoid increment and prefix (2), the new background (2), the residual (2) and the
@@ -426,6 +438,7 @@ def main():
 
     prof0 = s.profile()
     evals, lat, logz, stages = 0, [], [], []
+    moves_k = {K: 0 for K in ks}
     kinds = {"stage0": 0, "shape": 0, "linear": 0}
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -439,6 +452,8 @@ def main():
         lat.append(time.perf_counter() - ts)
         logz.append(s.log_evidence())
         stages.append(max(s.stage_info(K)[0] for K in ks))
+        for K in ks:
+            moves_k[K] += s.stage_info(K)[0]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof1 = s.profile()
@@ -460,31 +475,45 @@ def main():
         linear_slots = XRD_LINEAR[0] + TRANS_COST * XRD_LINEAR[1]
     elif spec.noise_kind == "poisson":
         shape_slots = SHAPE_POISSON[spec.peak_kind][0] + TRANS_COST * SHAPE_POISSON[spec.peak_kind][1]
-        linear_slots = LINEAR_POISSON[0] + TRANS_COST * LINEAR_POISSON[1]
+        linear_slots = LINEAR_POISSON[spec.peak_kind][0] + TRANS_COST * LINEAR_POISSON[spec.peak_kind][1]
     else:
         shape_slots = SHAPE_VALU[spec.peak_kind] + TRANS_COST * SHAPE_TRANS[spec.peak_kind]
-        linear_slots = LINEAR_VALU
+        linear_slots = LINEAR_VALU[spec.peak_kind]
     slots = (kinds["shape"] * shape_slots + kinds["linear"] * linear_slots) * spec.n
+    # the term switches of the Gaussian / pseudo-Voigt families (every term becomes the current
+    # one once per chain and sweep; chain-sweeps of a K per run = its moves x P, or x P n in
+    # standard mode)
+    switch_slots = 0.0
+    if spec.peak_kind in SWITCH_PEAK and spec.noise_kind != "hetero":
+        sv, st_ = SWITCH_PEAK[spec.peak_kind]
+        nb = {"none": 0, "const": 1, "linear": 2}[spec.bg_kind]
+        per_sweep = {K: K * (sv + TRANS_COST * st_) + SWITCH_BG_PER_COEFF * nb for K in ks}
+        sweeps_per_move = P if opt.waste_free else P * n
+        switch_slots = sum(moves_k[K] * sweeps_per_move * per_sweep[K] for K in ks) * spec.n
     move_units = (kinds["shape"] + kinds["linear"]) * spec.n
     launches = prof1["move_launches"] - prof0["move_launches"]
     move_s = (prof1["move_ms"] - prof0["move_ms"]) / 1e3
-    achieved = slots / move_s
+    achieved = (slots + switch_slots) / move_s
     bench_shape = args.workload == "xps-pv" and P == 65536 and not args.lanes
     traffic = recorded_traffic() if bench_shape else None
     insts = recorded_instructions() if bench_shape else None
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                 "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
                 "kernel": "k_move", "avg_launch_ms": move_s * 1e3 / max(launches, 1),
-                "ops_per_unit": slots / max(move_units, 1), "units_per_launch": move_units / max(launches, 1),
+                "ops_per_unit": (slots + switch_slots) / max(move_units, 1),
+                "units_per_launch": move_units / max(launches, 1),
                 "shape_evals": kinds["shape"], "linear_evals": kinds["linear"],
-                "slots_shape": shape_slots, "slots_linear": linear_slots}
+                "slots_shape": shape_slots, "slots_linear": linear_slots,
+                "switch_slots_per_launch": switch_slots / max(launches, 1),
+                "frac_proposals_only": slots / move_s / PEAK_LANE_OPS}
     if insts is not None:
         # executed VALU instructions (profile counters, transcendentals included) over the live
         # launch time: how close the kernel's instruction issue is to the VALU peak
         valu, trans = insts
         per_s = 64.0 * launches / move_s
         roofline["executed"] = {"valu_insts_per_launch": valu, "trans_insts_per_launch": trans,
-                                "frac_issue": valu * per_s / PEAK_LANE_OPS}
+                                "frac_issue": valu * per_s / PEAK_LANE_OPS,
+                                "executed_over_algorithmic": valu * 64.0 * launches / (slots + switch_slots)}
 
     out = {
         "metric": "particle*point likelihood evals/s",

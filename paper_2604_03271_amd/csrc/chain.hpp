@@ -33,8 +33,8 @@ namespace smc {
 
 // Points beyond N (the tile holds LC * PPL >= N) are loaded with x = kFarX,
 // where every peak profile underflows to 0 and the background is masked, and
-// with y = 0 (Gaussian noise) or y = -1 (Poisson, which the deviance term maps
-// to 0): they contribute exactly 0, so the point loops need no bounds.
+// with y = 0 (Gaussian noise: residual 0) or y = 1 and a model of 1 (Poisson:
+// deviance 0): they contribute exactly 0, so the point loops need no bounds.
 constexpr float kFarX = 1.0e18f;
 
 // The residual cache D and the shapes are rebuilt from the parameters every
@@ -68,6 +68,7 @@ struct ChainState {
     static constexpr bool kGaussNoise = NZ == SMC_NOISE_GAUSS;
     float x[PPL];
     float y[kGaussNoise ? 1 : PPL];
+    float cy[kGaussNoise ? 1 : PPL];   // Poisson: y ln y - y of the point's count
     float D[PPL];
     float S1[PPL];
     float S2[kPV ? PPL : 1];
@@ -78,7 +79,10 @@ struct ChainState {
             const int i = lane + p * LC;
             const bool ok = i < g.n;
             x[p] = ok ? g.x[i] : kFarX;
-            if constexpr (!kGaussNoise) y[p] = ok ? g.y[i] : -1.0f;
+            if constexpr (!kGaussNoise) {
+                y[p] = ok ? g.y[i] : 1.0f;
+                cy[p] = ok ? count_cy(y[p]) : 0.0f;
+            }
         }
     }
 
@@ -115,7 +119,7 @@ struct ChainState {
     // Energy term of point p given the residual r (Gaussian) or the model value f (Poisson).
     __device__ __forceinline__ float point_term(float rf, int p) const {
         if constexpr (kGaussNoise) return rf * rf;
-        else return poisson_dev(y[p], rf);
+        else return poisson_dev_cy(y[p], cy[p], rf);
     }
 
     static constexpr float kInclude = kGaussNoise ? -1.0f : 1.0f;
@@ -236,8 +240,10 @@ struct ChainState {
                 D[p] = i < g.n ? g.y[i] : 0.0f;
             }
         } else {
+            // a padding point's model stays 1 (its peaks underflow to 0, its background is
+            // masked), equal to its count 1: its deviance term is exactly 0
 #pragma unroll
-            for (int p = 0; p < PPL; ++p) D[p] = 0.0f;
+            for (int p = 0; p < PPL; ++p) D[p] = lane + p * LC < g.n ? 0.0f : 1.0f;
         }
         for (int k = kt - 1; k >= 1; --k) include(k == g.K, term_consts(g, th, k), false);
         const PeakC q0 = term_consts(g, th, 0);
@@ -299,6 +305,7 @@ __global__ void __launch_bounds__(256) k_energy(const GroupDesc* __restrict__ gr
     int parity = 0;
     float e = chain_sum<L, WPC>(cs.rebuild(g, th, lane), red, parity);
     if (NZ == SMC_NOISE_GAUSS) e *= g.inv2s2;
+    else e = poisson_energy(e);
     if (lane == 0) g.energy[i] = e;
 }
 
@@ -414,6 +421,7 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(
         else ++my_shape;
         float En = chain_sum<L, WPC>(part, red, parity);
         if (NZ == SMC_NOISE_GAUSS) En *= g.inv2s2;
+        else En = poisson_energy(En);
         const float log_alpha = -beta * (En - E) + prior_log_ratio(pr, vn, vo);
         if (chain_uniform<L>(lnu[j] < log_alpha)) {
             E = En;
@@ -445,6 +453,7 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(
             if (t % kRebuildEvery == 0) {
                 E = chain_sum<L, WPC>(cs.rebuild(g, th, lane), red, parity);
                 if (NZ == SMC_NOISE_GAUSS) E *= g.inv2s2;
+                else E = poisson_energy(E);
             } else if (kt > 1) {
                 cs.transition(g, th, kt - 1, 0);
             }

@@ -209,6 +209,33 @@ __device__ __forceinline__ float poisson_dev(float y, float f) {
     return y < 0.0f ? 0.0f : (f > 0.0f ? r : __builtin_inff());
 }
 
+// The same deviance term for a point with count y >= 0 and cy = y ln y - y (0 for y = 0)
+// precomputed: the series above for |v| < 0.1 (three terms, truncation below 3e-9 relative
+// there), else cy + f - y ln f, which is f - y + y ln(y/f) with the data's part folded into
+// cy (one log of f instead of a reciprocal and a log of y/f).  A model value f <= 0 has
+// |v| >= 1 (or v undefined), so it takes the direct form, which is then +inf (f = 0 < y) or
+// NaN (f < 0, or f = y = 0): a sum over points holding one is NaN or +inf, and
+// poisson_energy maps it to +inf once per energy instead of a test per point.  A padding point
+// carries y = f = 1, whose term is exactly 0 (v = 0 selects the series).
+__device__ __forceinline__ float poisson_dev_cy(float y, float cy, float f) {
+    const float d = y - f;
+    const float v = d * __builtin_amdgcn_rcpf(y + f);
+    const float v2 = v * v;
+    const float poly = __builtin_fmaf(v2, __builtin_fmaf(v2, 2.0f / 7.0f, 2.0f / 5.0f), 2.0f / 3.0f);
+    const float series = v * __builtin_fmaf(y * v2, poly, d);
+    const float direct = __builtin_fmaf(-y, kLn2 * __builtin_amdgcn_logf(f), cy + f);
+    return __builtin_fabsf(v) < 0.1f ? series : direct;
+}
+
+// A sum of poisson_dev_cy terms as an energy: NaN (some model value <= 0) becomes +inf.
+__device__ __forceinline__ float poisson_energy(float e) { return e == e ? e : __builtin_inff(); }
+
+// y ln y - y of a count, in FP64 and rounded once (0 for y = 0).
+__device__ __forceinline__ float count_cy(float y) {
+    const double yd = y;
+    return y > 0.0f ? static_cast<float>(yd * log(yd) - yd) : 0.0f;
+}
+
 // ---------------------------------------------------------------------------
 // Sum over the L consecutive lanes of a chain inside one wavefront.  Every step
 // is a butterfly whose two operands are swapped between partner lanes, so all

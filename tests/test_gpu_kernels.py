@@ -129,6 +129,32 @@ def test_energy_matches_reference(orc, peak, bg, noise, N, K, lanes):
     assert rel.max() <= 1e-5, (rel.max(), int(np.argmax(rel)))
 
 
+@pytest.mark.parametrize("peak,lanes", [("gauss", 0), ("pvoigt", 64), ("pvoigt", 32)])
+def test_poisson_energy_infinite_where_the_model_is_not_positive(orc, peak, lanes):
+    """Eq. xrd_poisson has no value where a model value is <= 0: energy +inf (R16), on the
+    GPU exactly where the reference gives +inf, finite energies within 1e-5 elsewhere."""
+    torch = torch_cuda()
+    rng = np.random.default_rng(77)
+    spec = W.random_spectrum(rng, 700, peak, "const", "poisson", k_true=2)
+    K = 2
+    th = _thetas(rng, spec, K, 64)
+    npk = 3 if peak == "gauss" else 4
+    b = npk * K
+    th[1::4, 0] = -3.0 * th[1::4, b]             # a peak deep below the background
+    th[2::4, b] = -1.0                           # a negative background
+    th = f32(th)
+    opr = orc.Problem(spec)
+    ref = np.array([orc.energy(opr, K, row) for row in th]) - energy_constant(spec)
+    say("poisson f <= 0", peak, lanes)
+    d_e = torch.zeros(len(th), dtype=torch.float32, device="cuda")
+    native.smc_kernel_energy(native.Problem(spec, K, K), K, dev(th.T.copy(), torch.float32), d_e, lanes=lanes)
+    got = d_e.cpu().numpy().astype(np.float64)
+    assert (~np.isfinite(ref)).sum() >= 16
+    assert np.array_equal(np.isinf(got), ~np.isfinite(ref)) and not np.any(np.isnan(got))
+    fin = np.isfinite(ref)
+    assert np.all(np.abs(got[fin] - ref[fin]) <= 1e-5 * np.abs(ref[fin]))
+
+
 def test_energy_every_tile_same_values(orc):
     """Every lane configuration evaluates the same energies (to rounding)."""
     torch = torch_cuda()
