@@ -314,8 +314,9 @@ __global__ void __launch_bounds__(256) k_energy(const GroupDesc* __restrict__ gr
 // Chain m starts from start[.][m]; standard mode writes its state after the
 // last sweep to particle m, waste-free mode writes the state after sweep t to
 // particle m * n + t (Sec. II.B.3).
-// LDS: the prior table [d]; per chain slot theta[d], increment s_j z_j [d], ln u_j [d] and
-// the chain's accept counters [d]; then the cross-wave reduction buffer.
+// LDS: per chain slot theta[d], increment s_j z_j [d], ln u_j [d] and the chain's accept
+// counters [d]; then the cross-wave reduction buffer (the prior table is read from global
+// memory with scalar loads: every lane of a chain proposes the same component).
 
 template <int PK, int NZ, int L, int WPC, int PPL>
 __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(const GroupDesc* __restrict__ groups,
@@ -336,8 +337,7 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(
     // chain's addresses and control flow are scalar too
     const int slot = L == 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / LC) : threadIdx.x / LC;
     const int lane = threadIdx.x % LC;
-    DevPrior* pri = reinterpret_cast<DevPrior*>(lds);   // [d], read once per proposal
-    float* body = lds + 4 * d;
+    float* body = lds;
     float* th = body + slot * 4 * d;
     float* inc = th + d;
     float* lnu = inc + d;
@@ -347,7 +347,7 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(
     uint32_t* nevals = reinterpret_cast<uint32_t*>(red + 2 * WPC);   // [0] shape, [1] linear
     // the proposal's shapes, [chain slot][point][lane], 8-byte aligned after the above
     constexpr int kSB = move_shape_lds_bytes(PK, NZ, PPL, LC);
-    float* shp = lds + ((4 * d + CPW * 4 * d + 2 * WPC + 2 + 1) & ~1);
+    float* shp = lds + ((CPW * 4 * d + 2 * WPC + 2 + 1) & ~1);
     float* my_shp = shp + (kSB / 4) * (slot * PPL * LC + lane);
 
     const bool active = slot < w.nchains;
@@ -357,7 +357,6 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(
     const uint32_t stage = static_cast<uint32_t>(st->stage);
     const uint32_t K = static_cast<uint32_t>(g.K);
 
-    for (int j = threadIdx.x; j < d; j += 256) pri[j] = g.prior[j];
     for (int j = threadIdx.x; j < CPW * d; j += 256) reinterpret_cast<uint32_t*>(body)[(j / d) * 4 * d + 3 * d + j % d] = 0u;
     if (threadIdx.x < 2) nevals[threadIdx.x] = 0u;
     uint32_t my_shape = 0, my_linear = 0;
@@ -386,7 +385,7 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(
         constexpr bool kAny = Q == kAnyComp;
         const int qi = Q < 0 ? q : Q;
         const int j = j0 + qi;
-        const DevPrior pr = pri[j];
+        const DevPrior pr = constant_load(g.prior + j);   // the same j in every lane: scalar loads
         if (pr.kind == SMC_PRIOR_FIXED) return;
         const float vo = tk[qi];
         const float vn = vo + inc[j];

@@ -275,7 +275,7 @@ __global__ void __launch_bounds__(256, xps_min_waves(PPL)) k_move_xps(const Grou
     extern __shared__ float lds[];
     const int slot = threadIdx.x / L, lane = threadIdx.x % L;
     DevPrior* pri = reinterpret_cast<DevPrior*>(lds);   // [d]
-    float* body = lds + 4 * d;
+    float* body = lds + kPriorFloats * d;
     float* th = body + slot * 3 * d;
     float* inc = th + d;
     float* lnu = inc + d;
@@ -283,7 +283,7 @@ __global__ void __launch_bounds__(256, xps_min_waves(PPL)) k_move_xps(const Grou
     uint32_t* nevals = reinterpret_cast<uint32_t*>(body + CPW * 3 * d + d + 2);   // [0] shape, [1] linear
     // the proposal's shapes, [chain slot][point][lane] float2, 8-byte aligned after the above
     constexpr int kSB = move_shape_lds_bytes(SMC_PEAK_PVOIGT, SMC_NOISE_HETERO, PPL, L);
-    float2* my_shp = reinterpret_cast<float2*>(lds + ((4 * d + CPW * 3 * d + d + 4 + 1) & ~1)) + (slot * PPL * L + lane);
+    float2* my_shp = reinterpret_cast<float2*>(lds + ((kPriorFloats * d + CPW * 3 * d + d + 4 + 1) & ~1)) + (slot * PPL * L + lane);
 
     const bool active = slot < w.nchains;
     const int m = w.chain0 + slot;

@@ -366,7 +366,7 @@ __global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256, xrd_min_waves(PP
     extern __shared__ float lds[];
     const int slot = threadIdx.x / LC, lane = threadIdx.x % LC;
     DevPrior* pri = reinterpret_cast<DevPrior*>(lds);
-    float* body = lds + 4 * d;
+    float* body = lds + kPriorFloats * d;
     float* th = body + slot * 3 * d;
     float* inc = th + d;
     float* lnu = inc + d;
@@ -375,7 +375,7 @@ __global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256, xrd_min_waves(PP
     uint32_t* nevals = reinterpret_cast<uint32_t*>(red + 2 * WPC);
     // the proposal's shapes, [chain slot][point][lane] float2, 8-byte aligned after the above
     constexpr int kSB = move_shape_lds_bytes(SMC_PEAK_XRD, SMC_NOISE_POISSON, PPL, LC);
-    float2* my_shp = reinterpret_cast<float2*>(lds + ((4 * d + CPW * 3 * d + d + 2 * WPC + 2 + 1) & ~1)) +
+    float2* my_shp = reinterpret_cast<float2*>(lds + ((kPriorFloats * d + CPW * 3 * d + d + 2 * WPC + 2 + 1) & ~1)) +
                      (slot * PPL * LC + lane);
 
     const bool active = slot < w.nchains;

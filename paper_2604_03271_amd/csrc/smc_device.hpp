@@ -85,11 +85,23 @@ __device__ inline float prior_draw(const DevPrior& pr, uint32_t k0, uint32_t k1,
     return pr.a;  // fixed
 }
 
-__device__ __forceinline__ bool prior_in_support(const DevPrior& pr, float v) {
-    if (pr.kind == SMC_PRIOR_UNIFORM) return v > pr.a && v < pr.b;
-    if (pr.kind == SMC_PRIOR_GAMMA) return v > 0.0f;
-    return __builtin_isfinite(v);
+// A read-only table entry loaded through the constant address space: with an index that is
+// the same in every lane the compiler issues scalar loads into scalar registers (the tables
+// read this way are not written while a kernel runs).
+template <typename T>
+__device__ __forceinline__ T constant_load(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "whole words");
+    using Word = const __attribute__((address_space(4))) uint32_t;
+    Word* w = reinterpret_cast<Word*>(reinterpret_cast<uintptr_t>(p));
+    uint32_t buf[sizeof(T) / 4];
+#pragma unroll
+    for (unsigned i = 0; i < sizeof(T) / 4; ++i) buf[i] = w[i];
+    return __builtin_bit_cast(T, buf);
 }
+
+// Inside the prior's support: the open interval (lo, hi) (uniform: (a, b); gamma: v > 0
+// and finite; normal: finite).
+__device__ __forceinline__ bool prior_in_support(const DevPrior& pr, float v) { return v > pr.lo && v < pr.hi; }
 
 // ln p(new) - ln p(old) for one component inside its support.
 __device__ __forceinline__ float prior_log_ratio(const DevPrior& pr, float vn, float vo) {
@@ -239,16 +251,17 @@ __device__ __forceinline__ float count_cy(float y) {
 // ---------------------------------------------------------------------------
 // Sum over the L consecutive lanes of a chain inside one wavefront.  Every step
 // is a butterfly whose two operands are swapped between partner lanes, so all
-// L lanes end with the same bits (IEEE addition is commutative).
+// L lanes end with the same bits (IEEE addition is commutative); a whole
+// wavefront ends in one scalar register.
 // ---------------------------------------------------------------------------
 template <int CTRL>
 __device__ __forceinline__ float dpp_swap(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
 }
 
-// Across rows the gfx950 permlane swaps (VALU, no LDS round trip) return the even
-// and the odd row of each pair of rows (16 lanes), or the low and the high half of
-// the wavefront (32 lanes), in every lane; all lanes add them in the same order.
+// Across rows the gfx950 permlane swap (VALU, no LDS round trip) returns the even
+// and the odd row of each pair of rows (16 lanes) in every lane; all lanes add them
+// in the same order.
 // The two results pass through an empty asm before they are added: this compiler
 // otherwise folds the sum of the swap's two results into twice the first one (seen in
 // the assembly as v_add_f32 vN, vN, vN after the swap), which is wrong.
@@ -263,10 +276,18 @@ __device__ __forceinline__ float row_pair_sum16(float v) {
     return swap_sum(p[0], p[1]);
 }
 
-__device__ __forceinline__ float half_pair_sum32(float v) {
-    const unsigned w = __builtin_bit_cast(unsigned, v);
-    const auto p = __builtin_amdgcn_permlane32_swap(w, w, false, false);
-    return swap_sum(p[0], p[1]);
+// v + (lane 15 of the row before) in rows 1 and 3, v elsewhere (one DPP add with a row mask;
+// the lanes of the rows the mask leaves out keep their value, so the operand is tied to the
+// result).  The s_nop gives the DPP read of v the wait states after the VALU write of v.
+__device__ __forceinline__ float add_row_bcast15(float v) {
+    asm volatile("s_nop 1\n\tv_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf" : "+v"(v));
+    return v;
+}
+
+// v + lane 31 in rows 2 and 3, v elsewhere.
+__device__ __forceinline__ float add_row_bcast31(float v) {
+    asm volatile("s_nop 1\n\tv_add_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf" : "+v"(v));
+    return v;
 }
 
 template <int L>
@@ -275,8 +296,14 @@ __device__ __forceinline__ float group_sum(float v) {
     v += dpp_swap<0x4E>(v);   // quad_perm [2,3,0,1]
     v += dpp_swap<0x141>(v);  // row_half_mirror: quads of a half-row
     v += dpp_swap<0x140>(v);  // row_mirror: halves of a 16-lane row
-    if constexpr (L >= 32) v = row_pair_sum16(v);
-    if constexpr (L >= 64) v = half_pair_sum32(v);
+    if constexpr (L == 32) v = row_pair_sum16(v);
+    if constexpr (L == 64) {
+        // a whole wavefront: the row sums added through DPP row broadcasts (row 1 += row 0,
+        // row 3 += row 2, then rows 2-3 += lane 31), the total read from lane 63 into a
+        // scalar register: one value for every lane, fewer instructions than two swaps
+        v = add_row_bcast31(add_row_bcast15(v));
+        v = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+    }
     return v;
 }
 

@@ -145,8 +145,19 @@ DevPrior dev_prior(const smc_prior& p) {
     d.a = static_cast<float>(p.a);
     d.b = static_cast<float>(p.b);
     d.c = 0.0f;
-    if (p.kind == SMC_PRIOR_GAMMA) d.c = static_cast<float>(p.a - 1.0);
-    if (p.kind == SMC_PRIOR_NORMAL) d.c = static_cast<float>(1.0 / (2.0 * p.b * p.b));
+    d.lo = d.a;
+    d.hi = d.a;
+    if (p.kind == SMC_PRIOR_UNIFORM) d.hi = d.b;
+    if (p.kind == SMC_PRIOR_GAMMA) {
+        d.c = static_cast<float>(p.a - 1.0);
+        d.lo = 0.0f;
+        d.hi = __builtin_inff();
+    }
+    if (p.kind == SMC_PRIOR_NORMAL) {
+        d.c = static_cast<float>(1.0 / (2.0 * p.b * p.b));
+        d.lo = -__builtin_inff();
+        d.hi = __builtin_inff();
+    }
     return d;
 }
 

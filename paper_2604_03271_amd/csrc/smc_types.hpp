@@ -16,11 +16,14 @@ enum { kPurposeInit = 1, kPurposeResample = 2, kPurposeMove = 3 };
 
 // Prior of one component in FP32 with the constant its log-density ratio needs:
 // gamma: c = shape - 1 (a = shape, b = rate); normal: c = 1 / (2 sd^2) (a = mean, b = sd);
-// uniform: a = lo, b = hi; fixed: a = value.
+// uniform: a = lo, b = hi; fixed: a = value.  The support is the open interval (lo, hi):
+// (a, b) uniform, (0, +inf) gamma, (-inf, +inf) normal (so NaN and infinities fall outside).
 struct DevPrior {
     int32_t kind;
     float a, b, c;
+    float lo, hi;
 };
+constexpr int kPriorFloats = static_cast<int>(sizeof(DevPrior) / sizeof(float));   // LDS floats per prior
 
 // Tempering state of a group (device resident).
 struct GroupState {
