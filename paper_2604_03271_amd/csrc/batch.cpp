@@ -90,10 +90,11 @@ size_t entry_bytes(const smc_problem& p, const smc_options& o) {
     return spectrum_bytes(p, o) + align256(sizeof(GroupState) * ng) + 4096;
 }
 
-// Lay out one entry inside [base, base + bytes): states first, then the spectrum's buffers.
-bool carve_entry(Entry& e, const smc_options& o, void* base) {
+// Lay out one entry inside [base, base + bytes): states first (or at `states`, a slot of a
+// table outside the block), then the spectrum's buffers.
+bool carve_entry(Entry& e, const smc_options& o, void* base, GroupState* states = nullptr) {
     Arena a{base, e.bytes, 0};
-    e.d_states = static_cast<GroupState*>(a.take(sizeof(GroupState) * e.ng));
+    e.d_states = states ? states : static_cast<GroupState*>(a.take(sizeof(GroupState) * e.ng));
     if (!e.d_states) return false;
     std::vector<PendingCopy> copies;
     e.groups.clear();
@@ -147,17 +148,20 @@ struct PoolView {
         cap_groups = cap_work = 0;
     }
 
-    // Rebuild from the entries (heaviest buckets and groups first) and upload.
-    smc_status rebuild(const std::vector<Entry*>& entries, hipStream_t s) {
+    // Rebuild from the entries (heaviest buckets and groups first) and upload.  With `keep`
+    // (one flag per group of the entries, in order) only the flagged groups enter the pool.
+    smc_status rebuild(const std::vector<Entry*>& entries, hipStream_t s, const std::vector<char>* keep = nullptr) {
         groups.clear();
         group_entry.clear();
         group_bucket.clear();
         buckets.clear();
         work.clear();
         std::map<std::tuple<int, int, int, int>, std::vector<int>> by_tile;
+        size_t flat = 0;
         for (size_t ei = 0; ei < entries.size(); ++ei) {
             const Entry& e = *entries[ei];
             for (int k = 0; k < e.ng; ++k) {
+                if (keep && !(*keep)[flat++]) continue;
                 const int gi = static_cast<int>(groups.size());
                 groups.push_back(e.groups[k]);
                 group_entry.push_back(static_cast<int>(ei));
@@ -320,8 +324,12 @@ extern "C" smc_status smc_batch_run(const smc_problem* probs, int32_t n, const s
         if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return SMC_EDEVICE;
         own = true;
     }
+    // one device block: the state table of every group (entries in order, so one copy reads
+    // them all), then the entries
     std::vector<std::unique_ptr<Entry>> entries(n);
-    size_t total = 0;
+    size_t ngroups = 0;
+    for (int i = 0; i < n; ++i) ngroups += probs[i].k_max - probs[i].k_min + 1;
+    size_t total = align256(sizeof(GroupState) * ngroups);
     for (int i = 0; i < n; ++i) {
         entries[i] = std::make_unique<Entry>();
         Entry& e = *entries[i];
@@ -341,9 +349,14 @@ extern "C" smc_status smc_batch_run(const smc_problem* probs, int32_t n, const s
     MoveWork* d_scratch = nullptr;
     size_t cap_scratch = 0;
     smc_status status = SMC_OK;
-    auto cleanup = [&]() {
+    auto drop_graph = [&]() {
         if (exec) hipGraphExecDestroy(exec);
         if (graph) hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    };
+    auto cleanup = [&]() {
+        drop_graph();
         hipStreamSynchronize(s);
         view.release();
         if (d_scratch) hipFree(d_scratch);
@@ -354,13 +367,17 @@ extern "C" smc_status smc_batch_run(const smc_problem* probs, int32_t n, const s
         cleanup();
         return SMC_ENOMEM;
     }
+    GroupState* d_states = static_cast<GroupState*>(dmem);
     std::vector<Entry*> ptrs;
     std::vector<std::vector<char>> keep;
+    size_t first = 0;
     for (auto& e : entries) {
-        if (!carve_entry(*e, *opt, static_cast<char*>(dmem) + e->off) || upload_entry(*e, s, keep) != hipSuccess) {
+        if (!carve_entry(*e, *opt, static_cast<char*>(dmem) + e->off, d_states + first) ||
+            upload_entry(*e, s, keep) != hipSuccess) {
             cleanup();
             return SMC_EDEVICE;
         }
+        first += e->ng;
         ptrs.push_back(e.get());
     }
     status = view.rebuild(ptrs, s);
@@ -372,18 +389,28 @@ extern "C" smc_status smc_batch_run(const smc_problem* probs, int32_t n, const s
         return status;
     }
 
-    // capture one stage (stage kernel + one move launch per bucket) and replay it
-    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) status = SMC_EDEVICE;
-    if (status == SMC_OK && view.launch_stage_all(s) != hipSuccess) status = SMC_EDEVICE;
-    if (hipStreamEndCapture(s, &graph) != hipSuccess && status == SMC_OK) status = SMC_EDEVICE;
-    if (status == SMC_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) status = SMC_EDEVICE;
+    // One stage of the pool (the stage pipeline over every group, one move launch per tile
+    // bucket) captured in a graph and replayed; after every few replays one copy reads all
+    // the states, and when groups have finished the pool is rebuilt without them and the
+    // stage captured again, so the tail of long runs launches only the groups still running.
+    auto capture = [&]() -> smc_status {
+        drop_graph();
+        smc_status cs = SMC_OK;
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return SMC_EDEVICE;
+        if (view.launch_stage_all(s) != hipSuccess) cs = SMC_EDEVICE;
+        if (hipStreamEndCapture(s, &graph) != hipSuccess && cs == SMC_OK) cs = SMC_EDEVICE;
+        if (cs == SMC_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) cs = SMC_EDEVICE;
+        return cs;
+    };
+    status = capture();
     if (status != SMC_OK) {
         cleanup();
         return status;
     }
 
-    const size_t ngroups = view.groups.size();
     std::vector<GroupState> states(ngroups);
+    std::vector<char> running(ngroups, 1);
+    size_t n_running = ngroups;
     const int replays_between_checks = 4;
     bool all_done = false;
     for (int round = 0; !all_done && round <= opt->max_stages + 2; round += replays_between_checks) {
@@ -392,27 +419,33 @@ extern "C" smc_status smc_batch_run(const smc_problem* probs, int32_t n, const s
                 cleanup();
                 return SMC_EDEVICE;
             }
+        if (hipMemcpyAsync(states.data(), d_states, sizeof(GroupState) * ngroups, hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            cleanup();
+            return SMC_EDEVICE;
+        }
         all_done = true;
-        if (copy_states(view, ptrs, states, s) != hipSuccess) {
-            cleanup();
-            return SMC_EDEVICE;
-        }
-        if (hipStreamSynchronize(s) != hipSuccess) {
-            cleanup();
-            return SMC_EDEVICE;
-        }
-        for (const GroupState& st : states) {
+        size_t still = 0;
+        for (size_t gi = 0; gi < ngroups; ++gi) {
+            const GroupState& st = states[gi];
             if (st.status != SMC_OK) status = st.status;
             all_done = all_done && st.done;
+            running[gi] = st.done ? 0 : 1;
+            still += running[gi];
         }
         if (status != SMC_OK) break;
+        if (!all_done && still < n_running) {
+            n_running = still;
+            status = view.rebuild(ptrs, s, &running);
+            if (status == SMC_OK) status = capture();
+            if (status != SMC_OK) break;
+        }
     }
     if (status == SMC_OK && !all_done) status = SMC_ENUMERIC;
     size_t o = 0;
-    for (size_t gi = 0; gi < ngroups; ++gi) {
-        const Entry& e = *entries[view.group_entry[gi]];
-        logz_out[o++] = states[gi].logz - states[gi].beta * e.econst;
-    }
+    for (const auto& e : entries)
+        for (int k = 0; k < e->ng; ++k, ++o) logz_out[o] = states[o].logz - states[o].beta * e->econst;
     cleanup();
     return status;
 }
