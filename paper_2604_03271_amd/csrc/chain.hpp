@@ -40,9 +40,9 @@ constexpr float kFarX = 1.0e18f;
 // The residual cache D and the shapes are rebuilt from the parameters every
 // kRebuildEvery sweeps (and at every chain start), which bounds the rounding
 // they accumulate through term-to-term updates: about 2(K+1) roundings of D per
-// sweep, a random walk of ~5e-7 relative after 8 sweeps, far below the 1e-5
-// energy tolerance (every 4 sweeps cost 2% more time).
-constexpr int kRebuildEvery = 8;
+// sweep, a random walk of ~7e-7 relative after 16 sweeps, far below the 1e-5
+// energy tolerance (every 8 sweeps: 1-2% more time, every 4: 3-4%).
+constexpr int kRebuildEvery = 16;
 
 // Component q of a peak enters its term linearly: amplitude (both kinds) and
 // Gaussian fraction (pseudo-Voigt).

@@ -76,7 +76,12 @@ struct XrdChain {
     // spill); a factor not cached is formed anew by every shape proposal.
     static constexpr bool kCW1 = PPL != 14;
     static constexpr bool kCW2 = PPL <= 10;
+    // y ln y - y of every count kept in registers where they allow it (up to 12 points per
+    // lane): the deviance then takes one log of the model value (poisson_dev_cy); beyond
+    // that the form with the ratio y / f (poisson_dev)
+    static constexpr bool kCY = PPL <= 12;
     float x[PPL], tn[PPL], y[PPL];
+    float cy[kCY ? PPL : 1];
     float D[PPL];
     float S1[PPL], S2[PPL];
     float W1[PPL], W2[PPL];   // width factors of the current term when it is a peak
@@ -90,6 +95,7 @@ struct XrdChain {
             const bool ok = i < g.n;
             x[p] = ok ? g.x[i] : kFarX;
             y[p] = ok ? g.y[i] : -1.0f;
+            if constexpr (kCY) cy[p] = ok ? count_cy(y[p]) : 0.0f;
             tn[p] = tanf(ok ? g.x[i] * kHalfRad : 0.0f);
         }
     }
@@ -154,13 +160,21 @@ struct XrdChain {
         return __builtin_fmaf(q.aL, l, __builtin_fmaf(q.aG, e, BG ? Dp + q.c0 : Dp));
     }
 
+    // The deviance term of point p at model value f; padding points (y = -1) give 0.  With
+    // the cached y ln y - y a model value <= 0 gives +inf or NaN, which the energy maps to +inf
+    // (poisson_energy); the other form tests it per point.
+    __device__ __forceinline__ float dev(int p, float f) const {
+        if constexpr (kCY) return y[p] < 0.0f ? 0.0f : poisson_dev_cy(y[p], cy[p], f);
+        else return poisson_dev(y[p], f);
+    }
+
     // Padding points (x = kFarX, y = -1) contribute 0: the deviance maps y < 0 to 0, and
     // their shapes are never evaluated into anything but that term.
     template <bool BG>
     __device__ __forceinline__ float partial_cached_t(const XrdC& q) const {
         float acc = 0.0f;
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) acc += poisson_dev(y[p], model<BG>(D[p], q, S1[p], S2[p]));
+        for (int p = 0; p < PPL; ++p) acc += dev(p, model<BG>(D[p], q, S1[p], S2[p]));
         return acc;
     }
 
@@ -193,7 +207,7 @@ struct XrdChain {
             float e, l;
             prop_shape<BG, MODE>(q, p, e, l, bad);
             if constexpr (STORE) sl[p * LC] = make_float2(e, l);
-            acc += poisson_dev(y[p], model<BG>(D[p], q, e, l));
+            acc += dev(p, model<BG>(D[p], q, e, l));
         }
         return bad ? __builtin_inff() : acc;
     }
@@ -311,7 +325,7 @@ struct XrdChain {
         set_shapes(false, q0);
         float acc = 0.0f;
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) acc += poisson_dev(y[p], model<false>(D[p], q0, S1[p], S2[p]));
+        for (int p = 0; p < PPL; ++p) acc += dev(p, model<false>(D[p], q0, S1[p], S2[p]));
         return (bad || wbad) ? __builtin_inff() : acc;
     }
 
@@ -345,7 +359,7 @@ __global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256) k_energy_xrd(con
     CS cs;
     cs.load_points(g, lane);
     int parity = 0;
-    const float e = chain_sum<L, WPC>(cs.rebuild(g, th), red, parity);
+    const float e = poisson_energy(chain_sum<L, WPC>(cs.rebuild(g, th), red, parity));
     if (lane == 0) g.energy[i] = e;
 }
 
@@ -412,7 +426,7 @@ __global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256, xrd_min_waves(PP
         }
         __syncthreads();
         if (active) {
-            if (t % kRebuildEvery == 0) E = chain_sum<L, WPC>(cs.rebuild(g, th), red, parity);
+            if (t % kRebuildEvery == 0) E = poisson_energy(chain_sum<L, WPC>(cs.rebuild(g, th), red, parity));
             else cs.transition(g, th, kt - 1, 0);
             for (int k = 0; k < kt; ++k) {
                 const bool is_bg = k == g.K;
@@ -434,7 +448,7 @@ __global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256, xrd_min_waves(PP
                     else part = cs.template partial_shape<(kSB > 0)>(is_bg, mode, qn, my_shp);
                     if (linear) ++my_linear;
                     else ++my_shape;
-                    const float En = chain_sum<L, WPC>(part, red, parity);
+                    const float En = poisson_energy(chain_sum<L, WPC>(part, red, parity));
                     const float log_alpha = -beta * (En - E) + prior_log_ratio(pr, vn, vo);
                     if (lnu[j] < log_alpha) {
                         E = En;
