@@ -577,12 +577,13 @@ def main():
     if not args.no_cpu_baseline:
         # the reference's leg: its timing on the host, and the FP64 check of the GPU's results
         progress("reference (CPU) leg")
-        out["cpu_baseline"] = cpu_baseline(spec, 5 if args.workload == "xps-pv" else spec.truth["K"])
+        cb = cpu_baseline(spec, 5 if args.workload == "xps-pv" else spec.truth["K"])
         if "config1" in out:
-            out["config1"]["oracle_end_to_end"] = config1_oracle()
-            out["config1"]["gpu_over_oracle"] = (out["config1"]["gpu_spectra_per_s"]
-                                                 / out["config1"]["oracle_end_to_end"]["spectra_per_s"])
-        out["fp64_check"] = fp64_check(native, spec, opt, s)
+            e2e = config1_oracle()
+            e2e["gpu_over_oracle"] = out["config1"]["gpu_spectra_per_s"] / e2e["spectra_per_s"]
+            cb["end_to_end_n201"] = e2e
+        cb["fp64_check"] = fp64_check(native, spec, opt, s)
+        out["cpu_baseline"] = cb
     s.close()
     print(json.dumps(out), flush=True)
 

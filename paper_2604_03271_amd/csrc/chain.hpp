@@ -67,8 +67,8 @@ struct ChainState {
     static constexpr bool kPV = PK == SMC_PEAK_PVOIGT;
     static constexpr bool kGaussNoise = NZ == SMC_NOISE_GAUSS;
     float x[PPL];
-    float y[kGaussNoise ? 1 : PPL];
-    float cy[kGaussNoise ? 1 : PPL];   // Poisson: y ln y - y of the point's count
+    float w[kGaussNoise ? 1 : PPL];    // Poisson: the point's count as count_w keeps it
+    float iw[kGaussNoise ? 1 : PPL];   // and its reciprocal
     float D[PPL];
     float S1[PPL];
     float S2[kPV ? PPL : 1];
@@ -80,8 +80,8 @@ struct ChainState {
             const bool ok = i < g.n;
             x[p] = ok ? g.x[i] : kFarX;
             if constexpr (!kGaussNoise) {
-                y[p] = ok ? g.y[i] : 1.0f;
-                cy[p] = ok ? count_cy(y[p]) : 0.0f;
+                w[p] = ok ? count_w(g.y[i]) : 1.0f;
+                iw[p] = 1.0f / w[p];
             }
         }
     }
@@ -116,10 +116,11 @@ struct ChainState {
         return x[p] < 1.0e17f ? bg_eval(x[p], q) : 0.0f;
     }
 
-    // Energy term of point p given the residual r (Gaussian) or the model value f (Poisson).
-    __device__ __forceinline__ float point_term(float rf, int p) const {
-        if constexpr (kGaussNoise) return rf * rf;
-        else return poisson_dev_cy(y[p], cy[p], rf);
+    // acc plus the energy term of point p given the residual r (Gaussian) or the model
+    // value f (Poisson).
+    __device__ __forceinline__ float point_term(float acc, float rf, int p) const {
+        if constexpr (kGaussNoise) return __builtin_fmaf(rf, rf, acc);
+        else return poisson_dev_acc(acc, w[p], iw[p], rf);
     }
 
     static constexpr float kInclude = kGaussNoise ? -1.0f : 1.0f;
@@ -129,7 +130,7 @@ struct ChainState {
     __device__ __forceinline__ float partial_linear(const PeakC& q) const {
         float acc = 0.0f;
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) acc += point_term(add_peak(D[p], kInclude, q, S1[p], s2(p)), p);
+        for (int p = 0; p < PPL; ++p) acc = point_term(acc, add_peak(D[p], kInclude, q, S1[p], s2(p)), p);
         return acc;
     }
 
@@ -140,7 +141,7 @@ struct ChainState {
         for (int p = 0; p < PPL; ++p) {
             float e, l;
             shape_at(q, p, e, l);
-            acc += point_term(add_peak(D[p], kInclude, q, e, l), p);
+            acc = point_term(acc, add_peak(D[p], kInclude, q, e, l), p);
         }
         return acc;
     }
@@ -149,7 +150,7 @@ struct ChainState {
     __device__ __forceinline__ float partial_bg(const PeakC& q) const {
         float acc = 0.0f;
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) acc += point_term(__builtin_fmaf(kInclude, bg_at(q, p), D[p]), p);
+        for (int p = 0; p < PPL; ++p) acc = point_term(acc, __builtin_fmaf(kInclude, bg_at(q, p), D[p]), p);
         return acc;
     }
 
@@ -163,7 +164,7 @@ struct ChainState {
             shape_at(q, p, e, l);
             if constexpr (kPV) reinterpret_cast<float2*>(sl)[p * LC] = make_float2(e, l);
             else sl[p * LC] = e;
-            acc += point_term(add_peak(D[p], kInclude, q, e, l), p);
+            acc = point_term(acc, add_peak(D[p], kInclude, q, e, l), p);
         }
         return acc;
     }

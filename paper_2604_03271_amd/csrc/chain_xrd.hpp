@@ -76,12 +76,11 @@ struct XrdChain {
     // spill); a factor not cached is formed anew by every shape proposal.
     static constexpr bool kCW1 = PPL != 14;
     static constexpr bool kCW2 = PPL <= 10;
-    // y ln y - y of every count kept in registers where they allow it (up to 12 points per
-    // lane): the deviance then takes one log of the model value (poisson_dev_cy); beyond
-    // that the form with the ratio y / f (poisson_dev)
-    static constexpr bool kCY = PPL <= 12;
-    float x[PPL], tn[PPL], y[PPL];
-    float cy[kCY ? PPL : 1];
+    // The reciprocal of every count (as count_w keeps it) held in registers where they
+    // allow it (up to 12 points per lane); beyond that each deviance term forms it (v_rcp).
+    static constexpr bool kIW = PPL <= 8;
+    float x[PPL], tn[PPL], w[PPL];
+    float iw[kIW ? PPL : 1];
     float D[PPL];
     float S1[PPL], S2[PPL];
     float W1[PPL], W2[PPL];   // width factors of the current term when it is a peak
@@ -94,8 +93,8 @@ struct XrdChain {
             const int i = lane + p * LC;
             const bool ok = i < g.n;
             x[p] = ok ? g.x[i] : kFarX;
-            y[p] = ok ? g.y[i] : -1.0f;
-            if constexpr (kCY) cy[p] = ok ? count_cy(y[p]) : 0.0f;
+            w[p] = ok ? count_w(g.y[i]) : -1.0f;
+            if constexpr (kIW) iw[p] = 1.0f / w[p];
             tn[p] = tanf(ok ? g.x[i] * kHalfRad : 0.0f);
         }
     }
@@ -160,21 +159,33 @@ struct XrdChain {
         return __builtin_fmaf(q.aL, l, __builtin_fmaf(q.aG, e, BG ? Dp + q.c0 : Dp));
     }
 
-    // The deviance term of point p at model value f; padding points (y = -1) give 0.  With
-    // the cached y ln y - y a model value <= 0 gives +inf or NaN, which the energy maps to +inf
-    // (poisson_energy); the other form tests it per point.
-    __device__ __forceinline__ float dev(int p, float f) const {
-        if constexpr (kCY) return y[p] < 0.0f ? 0.0f : poisson_dev_cy(y[p], cy[p], f);
-        else return poisson_dev(y[p], f);
+    // acc plus the deviance term of point p at model value f (poisson_dev_acc: a model
+    // value <= 0 makes the sum +inf or NaN, which the energy maps to +inf).  Padding points
+    // (x = kFarX), which only the rows from ppl_before(PPL) on hold (the tile rule), leave
+    // acc as it is: the constant background keeps their model away from 1.
+    __device__ __forceinline__ float dev(float acc, int p, float f) const {
+        float iwp;
+        if constexpr (kIW) {
+            iwp = iw[p];
+        } else {
+            // formed at every use: the empty asm keeps the compiler from hoisting the
+            // reciprocals out of the sweep loop into PPL more registers
+            float wp = w[p];
+            asm volatile("" : "+v"(wp));
+            iwp = __builtin_amdgcn_rcpf(wp);
+        }
+        const float r = poisson_dev_acc(acc, w[p], iwp, f);
+        if (p < ppl_before(PPL)) return r;
+        return w[p] > 0.0f ? r : acc;
     }
 
-    // Padding points (x = kFarX, y = -1) contribute 0: the deviance maps y < 0 to 0, and
-    // their shapes are never evaluated into anything but that term.
+    // Padding points contribute 0 (dev), and their shapes are never evaluated into anything
+    // but that term.
     template <bool BG>
     __device__ __forceinline__ float partial_cached_t(const XrdC& q) const {
         float acc = 0.0f;
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) acc += dev(p, model<BG>(D[p], q, S1[p], S2[p]));
+        for (int p = 0; p < PPL; ++p) acc = dev(acc, p, model<BG>(D[p], q, S1[p], S2[p]));
         return acc;
     }
 
@@ -207,7 +218,7 @@ struct XrdChain {
             float e, l;
             prop_shape<BG, MODE>(q, p, e, l, bad);
             if constexpr (STORE) sl[p * LC] = make_float2(e, l);
-            acc += dev(p, model<BG>(D[p], q, e, l));
+            acc = dev(acc, p, model<BG>(D[p], q, e, l));
         }
         return bad ? __builtin_inff() : acc;
     }
@@ -325,7 +336,7 @@ struct XrdChain {
         set_shapes(false, q0);
         float acc = 0.0f;
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) acc += dev(p, model<false>(D[p], q0, S1[p], S2[p]));
+        for (int p = 0; p < PPL; ++p) acc = dev(acc, p, model<false>(D[p], q0, S1[p], S2[p]));
         return (bad || wbad) ? __builtin_inff() : acc;
     }
 

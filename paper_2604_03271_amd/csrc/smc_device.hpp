@@ -202,51 +202,28 @@ __device__ __forceinline__ PeakC bg_consts(const float* th, int nbg) {
 
 __device__ __forceinline__ float bg_eval(float x, const PeakC& q) { return __builtin_fmaf(q.aL, x, q.aG); }
 
-// Poisson deviance term f - y + y ln(y/f) = f h((y-f)/f), h(u) = (1+u) ln(1+u) - u,
-// evaluated without cancellation: with v = (y-f)/(y+f) it equals
-// (y-f) v + 2 y v (v^2/3 + v^4/5 + v^6/7 + v^8/9 + ...) for |v| < 0.1 (Loader's
-// saddle-point deviance), and the direct form otherwise (y = 0 gives f there: the
-// ratio is floored at 1e-30, whose log times y = 0 is 0).  +inf if f <= 0; 0 for the
-// padding marker y < 0.
-__device__ __forceinline__ float poisson_dev(float y, float f) {
-    const float d = y - f;
-    const float v = d * __builtin_amdgcn_rcpf(y + f);
-    const float v2 = v * v;
-    const float series = __builtin_fmaf(
-        y * v,
-        v2 * __builtin_fmaf(v2, __builtin_fmaf(v2, __builtin_fmaf(v2, 2.0f / 9.0f, 2.0f / 7.0f), 2.0f / 5.0f), 2.0f / 3.0f),
-        d * v);
-    const float direct = __builtin_fmaf(y, fast_ln(__builtin_fmaxf(y * __builtin_amdgcn_rcpf(f), 1.0e-30f)), -d);
-    const float r = __builtin_fabsf(v) < 0.1f ? series : direct;
-    return y < 0.0f ? 0.0f : (f > 0.0f ? r : __builtin_inff());
+// Poisson deviance term of one point (Eq. xrd_poisson without its data-only part),
+// f - y + y ln(y/f) = y g(f/y) with g(u) = u - 1 - ln u, added to acc.  Each point keeps
+// w = count_w(y) and iw = 1/w, so the term takes a product, a subtraction, a log and two fmas:
+// acc + w g(u), u = f iw.  Near the fit (u near 1) g is about (u-1)^2/2 but u - 1 is exact
+// and the hardware log2 is accurate relative to its result, so the absolute error of the
+// term is about |f - y| 2.4e-7 (the roundings of iw, of u and of ln u); the sum over points
+// of such errors is far below the energies' 1e-5 relative tolerance.  A zero count is kept
+// as w = 2^-40 (count_w): the term is then f - w (1 + ln(f/w)), within 1e-10 of the exact f,
+// for any f below 2^88, where f iw would overflow.  f = 0 gives +inf (ln 0) and f < 0 NaN
+// (ln of a negative number): poisson_energy maps a sum holding NaN to +inf once per energy.
+// A padding point with y = f = 1 gives exactly 0.
+constexpr float kZeroCountW = 0x1p-40f;
+
+__device__ __forceinline__ float count_w(float y) { return y > 0.0f ? y : kZeroCountW; }
+
+__device__ __forceinline__ float poisson_dev_acc(float acc, float w, float iw, float f) {
+    const float u = f * iw;
+    return __builtin_fmaf(w, __builtin_fmaf(-kLn2, __builtin_amdgcn_logf(u), u - 1.0f), acc);
 }
 
-// The same deviance term for a point with count y >= 0 and cy = y ln y - y (0 for y = 0)
-// precomputed: the series above for |v| < 0.1 (three terms, truncation below 3e-9 relative
-// there), else cy + f - y ln f, which is f - y + y ln(y/f) with the data's part folded into
-// cy (one log of f instead of a reciprocal and a log of y/f).  A model value f <= 0 has
-// |v| >= 1 (or v undefined), so it takes the direct form, which is then +inf (f = 0 < y) or
-// NaN (f < 0, or f = y = 0): a sum over points holding one is NaN or +inf, and
-// poisson_energy maps it to +inf once per energy instead of a test per point.  A padding point
-// carries y = f = 1, whose term is exactly 0 (v = 0 selects the series).
-__device__ __forceinline__ float poisson_dev_cy(float y, float cy, float f) {
-    const float d = y - f;
-    const float v = d * __builtin_amdgcn_rcpf(y + f);
-    const float v2 = v * v;
-    const float poly = __builtin_fmaf(v2, __builtin_fmaf(v2, 2.0f / 7.0f, 2.0f / 5.0f), 2.0f / 3.0f);
-    const float series = v * __builtin_fmaf(y * v2, poly, d);
-    const float direct = __builtin_fmaf(-y, kLn2 * __builtin_amdgcn_logf(f), cy + f);
-    return __builtin_fabsf(v) < 0.1f ? series : direct;
-}
-
-// A sum of poisson_dev_cy terms as an energy: NaN (some model value <= 0) becomes +inf.
+// A sum of poisson_dev_acc terms as an energy: NaN (some model value <= 0) becomes +inf.
 __device__ __forceinline__ float poisson_energy(float e) { return e == e ? e : __builtin_inff(); }
-
-// y ln y - y of a count, in FP64 and rounded once (0 for y = 0).
-__device__ __forceinline__ float count_cy(float y) {
-    const double yd = y;
-    return y > 0.0f ? static_cast<float>(yd * log(yd) - yd) : 0.0f;
-}
 
 // ---------------------------------------------------------------------------
 // Sum over the L consecutive lanes of a chain inside one wavefront.  Every step
