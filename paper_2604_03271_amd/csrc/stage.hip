@@ -18,6 +18,89 @@
 
 namespace smc {
 
+// FP64 sums and minima over the 64 lanes of a wavefront (the stage kernels), the same bits
+// in every lane: each 64-bit exchange is two 32-bit DPP moves inside 16-lane rows, then the
+// permlane swaps across rows and halves (VALU only; a shuffle through ds_bpermute costs an
+// LDS round trip per step).
+template <int CTRL>
+__device__ __forceinline__ double dpp_swap64(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = static_cast<uint32_t>(
+        __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<uint32_t>(b)), CTRL, 0xF, 0xF, false));
+    const uint32_t hi = static_cast<uint32_t>(
+        __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<uint32_t>(b >> 32)), CTRL, 0xF, 0xF, false));
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// The two values of v that a permlane swap pairs (rows 2r and 2r+1 for the 16-lane swap,
+// the two halves for the 32-lane one), in the same order in every lane; the empty asm keeps
+// the compiler from folding the pair (see swap_sum).
+template <bool HALVES>
+__device__ __forceinline__ void swap_pair64(double v, double& a, double& b) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const unsigned lo = static_cast<unsigned>(u), hi = static_cast<unsigned>(u >> 32);
+    unsigned l0, l1, h0, h1;
+    if constexpr (HALVES) {
+        const auto pl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto ph = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        l0 = pl[0]; l1 = pl[1]; h0 = ph[0]; h1 = ph[1];
+    } else {
+        const auto pl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto ph = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        l0 = pl[0]; l1 = pl[1]; h0 = ph[0]; h1 = ph[1];
+    }
+    asm volatile("" : "+v"(l0), "+v"(l1), "+v"(h0), "+v"(h1));
+    a = __builtin_bit_cast(double, (static_cast<uint64_t>(h0) << 32) | l0);
+    b = __builtin_bit_cast(double, (static_cast<uint64_t>(h1) << 32) | l1);
+}
+
+__device__ __forceinline__ double wave_sum64(double v) {
+    v += dpp_swap64<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_swap64<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_swap64<0x141>(v);  // row_half_mirror
+    v += dpp_swap64<0x140>(v);  // row_mirror
+    double a, b;
+    swap_pair64<false>(v, a, b);
+    v = a + b;
+    swap_pair64<true>(v, a, b);
+    return a + b;
+}
+
+__device__ __forceinline__ double wave_min64(double v) {
+    v = fmin(v, dpp_swap64<0xB1>(v));
+    v = fmin(v, dpp_swap64<0x4E>(v));
+    v = fmin(v, dpp_swap64<0x141>(v));
+    v = fmin(v, dpp_swap64<0x140>(v));
+    double a, b;
+    swap_pair64<false>(v, a, b);
+    v = fmin(a, b);
+    swap_pair64<true>(v, a, b);
+    return fmin(a, b);
+}
+
+// Inclusive prefix sum of a 64-bit integer over the 64 lanes of a wavefront (exact): shifts
+// by 1, 2, 4, 8 lanes inside each 16-lane row, then each row total broadcast into the rows
+// after it (DPP row_bcast:15 into rows 1 and 3, row_bcast:31 into rows 2 and 3).  Lanes that a
+// shift or a row mask leaves out receive 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+    const uint32_t lo = static_cast<uint32_t>(
+        __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<uint32_t>(v)), CTRL, ROWS, 0xF, false));
+    const uint32_t hi = static_cast<uint32_t>(
+        __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<uint32_t>(v >> 32)), CTRL, ROWS, 0xF, false));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
+    v += dpp_u64<0x111, 0xF>(v);   // row_shr:1
+    v += dpp_u64<0x112, 0xF>(v);   // row_shr:2
+    v += dpp_u64<0x114, 0xF>(v);   // row_shr:4
+    v += dpp_u64<0x118, 0xF>(v);   // row_shr:8
+    v += dpp_u64<0x142, 0xA>(v);   // row_bcast:15
+    v += dpp_u64<0x143, 0xC>(v);   // row_bcast:31
+    return v;
+}
+
 constexpr int kStageThreads = 1024;
 constexpr int kStageWaves = kStageThreads / 64;
 
@@ -31,9 +114,7 @@ struct StageShared {
 template <int NV>
 __device__ inline void block_sum(double* v, StageShared& sh) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-        for (int q = 0; q < NV; ++q) v[q] += __shfl_xor(v[q], o, 64);
+    for (int q = 0; q < NV; ++q) v[q] = wave_sum64(v[q]);
     const int w = threadIdx.x >> 6;
     __syncthreads();
     if ((threadIdx.x & 63) == 0)
@@ -102,8 +183,7 @@ __device__ inline BisectOut bisect(const float* E, int P, double beta, double rh
         }
         emin = fmin(emin, static_cast<double>(e));
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) emin = fmin(emin, __shfl_xor(emin, off, 64));
+    emin = wave_min64(emin);
     __syncthreads();
     if ((threadIdx.x & 63) == 0) sh.red[3][threadIdx.x >> 6] = emin;  // read before block_sum reuses red
     __syncthreads();
@@ -248,9 +328,7 @@ __device__ inline double* part_buf(const GroupDesc& g, int parity) {
 template <int NV>
 __device__ inline void chunk_block_sum(double* v, double (*red)[kChunkWaves]) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-        for (int q = 0; q < NV; ++q) v[q] += __shfl_xor(v[q], o, 64);
+    for (int q = 0; q < NV; ++q) v[q] = wave_sum64(v[q]);
     const int w = threadIdx.x >> 6;
     __syncthreads();
     if ((threadIdx.x & 63) == 0)
@@ -271,6 +349,13 @@ __device__ inline void chunk_block_sum(double* v, double (*red)[kChunkWaves]) {
 // MIN_LAST is set.
 template <int NV, bool MIN_LAST>
 __device__ inline void reduce_parts(const double* parts, int nchunk, double* out, double (*red)[kChunkWaves]) {
+    if (nchunk == 1) {
+        // one chunk: what the tree below returns for it (its partials plus zeros, or the
+        // minimum with +inf), without the block reduction
+#pragma unroll
+        for (int q = 0; q < NV; ++q) out[q] = (MIN_LAST && q == NV - 1) ? fmin(__builtin_inf(), parts[q]) : 0.0 + parts[q];
+        return;
+    }
     double v[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) v[q] = (MIN_LAST && q == NV - 1) ? __builtin_inf() : 0.0;
@@ -284,8 +369,7 @@ __device__ inline void reduce_parts(const double* parts, int nchunk, double* out
     }
     if constexpr (MIN_LAST) {
         double m = v[NV - 1];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, 64));
+        m = wave_min64(m);
         __syncthreads();
         if ((threadIdx.x & 63) == 0) red[0][threadIdx.x >> 6] = m;
         __syncthreads();
@@ -467,8 +551,7 @@ __device__ inline void st_stats(const GroupDesc* __restrict__ groups, int gi, in
         }
     }
     double m = v[4];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, 64));
+    m = wave_min64(m);
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[5][threadIdx.x >> 6] = m;
     chunk_block_sum<4>(v, red);
@@ -634,12 +717,7 @@ __device__ inline void st_quantise(const GroupDesc* __restrict__ groups, int gi,
         local += q[k];
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    unsigned long long incl = local;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const unsigned long long v = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += v;
-    }
+    const unsigned long long incl = wave_incl_scan_u64(local);
     __syncthreads();   // every weight of the chunk read before any is overwritten
     if (lane == 63) s_scan[wv] = incl;
     __syncthreads();
@@ -679,12 +757,7 @@ __device__ inline void st_offsets(const GroupDesc* __restrict__ groups, int gi) 
     for (int c0 = 0; c0 < g.nchunk; c0 += kChunkThreads) {
         const int c = c0 + static_cast<int>(threadIdx.x);
         const unsigned long long v = c < g.nchunk ? g.ctot[c] : 0ull;
-        unsigned long long incl = v;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const unsigned long long u = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += u;
-        }
+        const unsigned long long incl = wave_incl_scan_u64(v);
         if (lane == 63) s_scan[wv] = incl;
         __syncthreads();
         unsigned long long off = s_carry + incl - v;
@@ -798,12 +871,53 @@ __global__ void __launch_bounds__(kChunkThreads) k_st_adapt(const GroupDesc* __r
 // the order of its own launch, so the results are those of the chunk-parallel launches bit
 // for bit; the stage costs four launches instead of seventeen (the step sizes keep their
 // own launch, one workgroup per component).
+// The passes of st_search for a group of one chunk, inside its workgroup: the search state
+// and the weight sums stay in the workgroup (LDS and registers) between passes instead of
+// going through the global buffers that separate launches need, and the passes stop once the
+// search has ended.  The same steps on the same sums (a one-chunk reduction of the partials
+// is the partial plus zero), so the same bits; the final state goes where k_st_finish and the
+// weights read it.
+__device__ inline void st_search_one_chunk(const GroupDesc* __restrict__ groups, int gi) {
+    const GroupDesc& g = groups[gi];
+    GroupState* st = g.st;
+    if (st->done) return;
+    __shared__ double red[kStagePartVals][kChunkWaves];
+    __shared__ StageNewton s_nst;
+    double sums[5];
+    reduce_parts<5, true>(part_buf(g, 0), 1, sums, red);
+    StageNewton ns{};
+    int i0, i1;
+    chunk_range(g, 0, i0, i1);
+    for (int it = 0; it < kNewtonLaunches; ++it) {
+        if (threadIdx.x == 0) {
+            ns = search_step(g, ns, sums, it, st->beta);
+            s_nst = ns;
+            if (ns.phase == kPhaseFail) {
+                st->status = SMC_ENUMERIC;
+                st->done = 1;
+            }
+        }
+        __syncthreads();
+        ns = s_nst;
+        if (ns.phase != kPhaseH && ns.phase != kPhaseNewton) break;
+        if (it + 1 == kNewtonLaunches) break;   // no pass left to use the sums
+        double out[4];
+        if (ns.phase == kPhaseH) {
+            chunk_weight_sums<2>(g.energy, i0, i1, ns.emin, ns.x, out, nullptr, red);
+            out[2] = out[3] = 0.0;
+        } else {
+            chunk_weight_sums<4>(g.energy, i0, i1, ns.emin, ns.x, out, nullptr, red);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sums[q] = 0.0 + out[q];
+    }
+    if (threadIdx.x == 0) *nst_buf(g, kNewtonLaunches) = ns;
+}
+
 __global__ void __launch_bounds__(kChunkThreads) k_st_pre1(const GroupDesc* __restrict__ groups) {
     st_stats(groups, blockIdx.x, 0);
-    for (int it = 0; it < kNewtonLaunches; ++it) {
-        __syncthreads();
-        st_search(groups, blockIdx.x, 0, it);
-    }
+    __syncthreads();
+    st_search_one_chunk(groups, blockIdx.x);
 }
 
 __global__ void __launch_bounds__(kChunkThreads) k_st_post1(const GroupDesc* __restrict__ groups, int mblocks) {
