@@ -54,9 +54,17 @@ __device__ __forceinline__ float chain_scan(float v, float& total) {
     }
 }
 
+// A chain's energy from its summed shares: NaN (a variance <= 0 somewhere) becomes +inf.
+__device__ __forceinline__ float xps_energy(float e) { return e == e ? e : __builtin_inff(); }
+
 template <int L, int PPL>
 struct XpsChain {
+    // Point widths x[p] - x[p - 1] (the lane's first point: minus the previous lane's last x)
+    // kept in registers from 12 points per lane on, where the tile runs two waves per SIMD
+    // anyway; below that they are formed at each use (keeping them would cost a wave).
+    static constexpr bool kDX = PPL >= 12;
     float x[PPL];
+    float dx[kDX ? PPL : 1];
     float y[PPL];
     float R[PPL];   // y - (sum of all peaks)
     float S1[PPL];  // current peak: exp2(c t^2)
@@ -67,6 +75,7 @@ struct XpsChain {
     float x1, xspan;  // first point and x_N - x_1 (flat-limit background)
     int nvalid;     // points of this lane below N
     int lane;       // lane inside the chain
+    bool whole;     // every lane of the wavefront holds all PPL of its points below N, or none
 
     // Points beyond N repeat the last x, so their trapezoid widths are 0, and are masked
     // out of the energy.
@@ -80,7 +89,14 @@ struct XpsChain {
             x[p] = g.x[i];
             y[p] = i0 + p < g.n ? g.y[i] : 0.0f;
         }
+        // the padding is whole lanes (N a multiple of PPL): the point loops then need no
+        // per-point masks, and a lane without points drops its sums
+        whole = __builtin_amdgcn_ballot_w64(nvalid != 0 && nvalid != PPL) == 0;
         xprev = ln == 0 ? x[0] : g.x[min(i0, g.n) - 1];
+        if constexpr (kDX) {
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) dx[p] = x[p] - (p == 0 ? xprev : x[p - 1]);
+        }
         x1 = g.x[0];
         xspan = g.x[g.n - 1] - g.x[0];
     }
@@ -108,24 +124,31 @@ struct XpsChain {
     }
 
     // Twice the trapezoid increments of v over this lane's points, prefix-summed over the
-    // chain into out (inclusive); returns the chain total.  The point widths are formed from
-    // copies of x that an empty asm makes opaque, so that the compiler does not hoist them
-    // out of the sweep loop into PPL more live registers.
+    // chain into out (inclusive); returns the chain total.  Without kDX the point widths are
+    // formed from copies of x that an empty asm makes opaque, so that the compiler does not
+    // hoist them out of the sweep loop into PPL more live registers.
     __device__ __forceinline__ float integrate(const float* v, float* out) const {
         float vprev = __shfl_up(v[PPL - 1], 1, L);
         if (lane == 0) vprev = 0.0f;   // width 0 at the first point; keep NaN-free
-        float xs[PPL];
+        float w[PPL];
+        if constexpr (kDX) {
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-            xs[p] = x[p];
-            asm volatile("" : "+v"(xs[p]));
+            for (int p = 0; p < PPL; ++p) w[p] = dx[p];
+        } else {
+            float xp = xprev;
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) {
+                float xs = x[p];
+                asm volatile("" : "+v"(xs));
+                w[p] = xs - xp;
+                xp = xs;
+            }
         }
-        float run = 0.0f, xp = xprev;
+        float run = 0.0f;
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
-            run = __builtin_fmaf(xs[p] - xp, vprev + v[p], run);
+            run = __builtin_fmaf(w[p], vprev + v[p], run);
             out[p] = run;
-            xp = xs[p];
             vprev = v[p];
         }
         float total;
@@ -153,29 +176,38 @@ struct XpsChain {
         return __builtin_fmaf(b - a, u, a);
     }
 
-    // Energy (without (N/2) ln 2 pi) of residuals r_p = rr_p - B_p, over this lane's points.
-    __device__ __forceinline__ static void noise_term(float r, float yp, const float* hn, float& accl, float& accq,
-                                                      bool& bad) {
+    // Energy terms (without (N/2) ln 2 pi) of point p with residual r: ln of the variance
+    // into accl, r^2 over the variance into accq.  A variance <= 0 (energy +inf, R22) makes
+    // the sums NaN (the log of a negative number, or -inf + inf, or 0 * inf), which
+    // xps_energy maps to +inf once per energy instead of a test per point.
+    __device__ __forceinline__ static void noise_term(float r, float yp, const float* hn, float& accl, float& accq) {
         const float f = yp - r;
         const float v = __builtin_fmaf(__builtin_fmaf(hn[1], f, hn[0]), f, hn[2]);
-        bad |= !(v > 0.0f);
         accl += __builtin_amdgcn_logf(v);
         accq = __builtin_fmaf(r * r, __builtin_amdgcn_rcpf(v), accq);
     }
 
-    __device__ __forceinline__ static float finish(float accl, float accq, bool bad) {
-        return bad ? __builtin_inff() : 0.5f * __builtin_fmaf(kLn2, accl, accq);
+    // The lane's energy share from its sums over points p < nvalid: every point when the
+    // padding is whole lanes (a lane without points then returns 0), else a mask per point.
+    template <typename Resid>
+    __device__ __forceinline__ float energy_share(const float* hn, Resid resid) const {
+        float accl = 0.0f, accq = 0.0f;
+        if (whole) {
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) noise_term(resid(p), y[p], hn, accl, accq);
+            if (nvalid == 0) accl = accq = 0.0f;
+        } else {
+#pragma unroll
+            for (int p = 0; p < PPL; ++p)
+                if (p < nvalid) noise_term(resid(p), y[p], hn, accl, accq);
+        }
+        return 0.5f * __builtin_fmaf(kLn2, accl, accq);
     }
 
     // Energy share of the current state with background (a, b).
     __device__ __forceinline__ float partial_state(const float* hn, float a, float b) const {
         const BgWeights w = bg_weights(CN);
-        float accl = 0.0f, accq = 0.0f;
-        bool bad = false;
-#pragma unroll
-        for (int p = 0; p < PPL; ++p)
-            if (p < nvalid) noise_term(R[p] - background(C[p], w, p, a, b), y[p], hn, accl, accq, bad);
-        return finish(accl, accq, bad);
+        return energy_share(hn, [&](int p) { return R[p] - background(C[p], w, p, a, b); });
     }
 
     // Proposal changing the current peak from qo to qn: d = change of the peak's values,
@@ -185,22 +217,22 @@ struct XpsChain {
     template <bool kShape, bool kStore = false>
     __device__ __forceinline__ float partial_peak(const PeakC& qo, const PeakC& qn, const float* hn, float a, float b,
                                                   float* d, float* dC, float& dCN, float2* sl = nullptr) const {
+        // a linear proposal keeps the shapes: the change is (delta aG) e + (delta aL) l
+        const float dG = qn.aG - qo.aG, dL = qn.aL - qo.aL;
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
-            float e = S1[p], l = S2[p];
-            if constexpr (kShape) shape_at(qn, p, e, l);
-            if constexpr (kShape && kStore) sl[p * L] = make_float2(e, l);
-            d[p] = value(qn, e, l) - value(qo, S1[p], S2[p]);
+            if constexpr (kShape) {
+                float e, l;
+                shape_at(qn, p, e, l);
+                if constexpr (kStore) sl[p * L] = make_float2(e, l);
+                d[p] = value(qn, e, l) - value(qo, S1[p], S2[p]);
+            } else {
+                d[p] = __builtin_fmaf(dL, S2[p], dG * S1[p]);
+            }
         }
         dCN = integrate(d, dC);
         const BgWeights w = bg_weights(CN + dCN);
-        float accl = 0.0f, accq = 0.0f;
-        bool bad = false;
-#pragma unroll
-        for (int p = 0; p < PPL; ++p)
-            if (p < nvalid)
-                noise_term((R[p] - d[p]) - background(C[p] + dC[p], w, p, a, b), y[p], hn, accl, accq, bad);
-        return finish(accl, accq, bad);
+        return energy_share(hn, [&](int p) { return (R[p] - d[p]) - background(C[p] + dC[p], w, p, a, b); });
     }
 
     __device__ __forceinline__ void accept_peak(const float* d, const float* dC, float dCN) {
@@ -256,7 +288,7 @@ __global__ void __launch_bounds__(256) k_energy_xps(const GroupDesc* __restrict_
     if (!active) return;
     XpsChain<L, PPL> cs;
     cs.load_points(g, lane);
-    const float e = group_sum<L>(cs.rebuild(g, th));
+    const float e = xps_energy(group_sum<L>(cs.rebuild(g, th)));
     if (lane == 0) g.energy[i] = e;
 }
 
@@ -319,7 +351,7 @@ __global__ void __launch_bounds__(256, xps_min_waves(PPL)) k_move_xps(const Grou
         }
         __syncthreads();
         if (active) {
-            if (t % kXpsRebuildEvery == 0) E = group_sum<L>(cs.rebuild(g, th));
+            if (t % kXpsRebuildEvery == 0) E = xps_energy(group_sum<L>(cs.rebuild(g, th)));
             else cs.set_shapes(peak_consts<SMC_PEAK_PVOIGT>(th));
             for (int k = 0; k <= g.K; ++k) {
                 const bool is_bg = k == g.K;
@@ -351,7 +383,7 @@ __global__ void __launch_bounds__(256, xps_min_waves(PPL)) k_move_xps(const Grou
                     }
                     if (linear) ++my_linear;
                     else ++my_shape;
-                    const float En = group_sum<L>(part);
+                    const float En = xps_energy(group_sum<L>(part));
                     const float log_alpha = -beta * (En - E) + prior_log_ratio(pr, vn, vo);
                     if (lnu[j] < log_alpha) {
                         E = En;
