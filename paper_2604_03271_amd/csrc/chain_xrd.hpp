@@ -307,16 +307,16 @@ struct XrdChain {
         return k < g.K ? xrd_peak_consts(th + k * g.np, g.mu_ref[k]) : xrd_bg_consts(th + g.K * g.np);
     }
 
-    // Constants of term k with its component q replaced by vn (registers only: the chain's
-    // parameter vector in LDS is shared by all its lanes).
+    // Constants of term k with its component q replaced by vn, formed from the chain's
+    // parameter vector in LDS (mref: the peak's reference position).
     __device__ __forceinline__ static XrdC term_consts_with(const GroupDesc& g, const float* th, int k, int q,
-                                                            float vn) {
+                                                            float vn, float mref) {
         if (k < g.K) {
             float t9[9];
             const float* b = th + k * 9;
 #pragma unroll
             for (int u = 0; u < 9; ++u) t9[u] = u == q ? vn : b[u];
-            return xrd_peak_consts(t9, g.mu_ref[k]);
+            return xrd_peak_consts(t9, mref);
         }
         float t4[4];
         const float* b = th + g.K * 9;
@@ -390,7 +390,6 @@ __global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256, xrd_min_waves(PP
 
     extern __shared__ float lds[];
     const int slot = threadIdx.x / LC, lane = threadIdx.x % LC;
-    DevPrior* pri = reinterpret_cast<DevPrior*>(lds);
     float* body = lds + kPriorFloats * d;
     float* th = body + slot * 3 * d;
     float* inc = th + d;
@@ -410,10 +409,7 @@ __global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256, xrd_min_waves(PP
     const uint32_t stage = static_cast<uint32_t>(st->stage);
     const uint32_t K = static_cast<uint32_t>(g.K);
 
-    for (int j = threadIdx.x; j < d; j += TPB) {
-        accc[j] = 0u;
-        pri[j] = g.prior[j];
-    }
+    for (int j = threadIdx.x; j < d; j += TPB) accc[j] = 0u;
     if (threadIdx.x < 2) nevals[threadIdx.x] = 0u;
     uint32_t my_shape = 0, my_linear = 0;
     float E = 0.0f;
@@ -444,14 +440,18 @@ __global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256, xrd_min_waves(PP
                 const int j0 = is_bg ? g.K * g.np : k * g.np;
                 const int nq = is_bg ? g.nbg : g.np;
                 if (k > 0) cs.transition(g, th, k - 1, k);
+                // the current peak's reference position, read once per term (each proposal
+                // forms its constants from the chain's parameter vector; keeping them all in
+                // registers between proposals measured slower at 4 points per lane)
+                const float mref = is_bg ? 0.0f : g.mu_ref[k];
                 for (int q = 0; q < nq; ++q) {
                     const int j = j0 + q;
-                    const DevPrior pr = pri[j];
+                    const DevPrior pr = constant_load(g.prior + j);   // one component per chain: scalar loads
                     if (pr.kind == SMC_PRIOR_FIXED) continue;
                     const float vo = th[j];
                     const float vn = vo + inc[j];
-                    if (!prior_in_support(pr, vn)) continue;
-                    const XrdC qn = CS::term_consts_with(g, th, k, q, vn);
+                    if (!chain_uniform<L>(prior_in_support(pr, vn))) continue;
+                    const XrdC qn = CS::term_consts_with(g, th, k, q, vn, mref);
                     const bool linear = xrd_linear(is_bg, q);
                     const int mode = is_bg ? kXrdCachedW : xrd_peak_mode(q);
                     float part;
@@ -461,7 +461,7 @@ __global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256, xrd_min_waves(PP
                     else ++my_shape;
                     const float En = poisson_energy(chain_sum<L, WPC>(part, red, parity));
                     const float log_alpha = -beta * (En - E) + prior_log_ratio(pr, vn, vo);
-                    if (lnu[j] < log_alpha) {
+                    if (chain_uniform<L>(lnu[j] < log_alpha)) {
                         E = En;
                         if (!linear) cs.template accept_shape<(kSB > 0)>(is_bg, mode, qn, my_shp);
                         th[j] = vn;
