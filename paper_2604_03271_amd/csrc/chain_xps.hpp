@@ -306,7 +306,6 @@ __global__ void __launch_bounds__(256, xps_min_waves(PPL)) k_move_xps(const Grou
 
     extern __shared__ float lds[];
     const int slot = threadIdx.x / L, lane = threadIdx.x % L;
-    DevPrior* pri = reinterpret_cast<DevPrior*>(lds);   // [d]
     float* body = lds + kPriorFloats * d;
     float* th = body + slot * 3 * d;
     float* inc = th + d;
@@ -325,10 +324,7 @@ __global__ void __launch_bounds__(256, xps_min_waves(PPL)) k_move_xps(const Grou
     const uint32_t K = static_cast<uint32_t>(g.K);
     const int np = g.np, jbg = g.K * g.np;
 
-    for (int j = threadIdx.x; j < d; j += 256) {
-        accc[j] = 0u;
-        pri[j] = g.prior[j];
-    }
+    for (int j = threadIdx.x; j < d; j += 256) accc[j] = 0u;
     if (threadIdx.x < 2) nevals[threadIdx.x] = 0u;
     uint32_t my_shape = 0, my_linear = 0;
     float E = 0.0f;
@@ -360,11 +356,11 @@ __global__ void __launch_bounds__(256, xps_min_waves(PPL)) k_move_xps(const Grou
                 const int nq = is_bg ? g.nbg : np;
                 for (int q = 0; q < nq; ++q) {
                     const int j = j0 + q;
-                    const DevPrior pr = pri[j];
+                    const DevPrior pr = constant_load(g.prior + j);   // one component per chain: scalar loads
                     if (pr.kind == SMC_PRIOR_FIXED) continue;
                     const float vo = th[j];
                     const float vn = vo + inc[j];
-                    if (!prior_in_support(pr, vn)) continue;
+                    if (!chain_uniform<L>(prior_in_support(pr, vn))) continue;
                     float part, dCN = 0.0f;
                     PeakC qn{};
                     const bool linear = is_bg || linear_component<SMC_PEAK_PVOIGT>(q);
@@ -385,7 +381,7 @@ __global__ void __launch_bounds__(256, xps_min_waves(PPL)) k_move_xps(const Grou
                     else ++my_shape;
                     const float En = xps_energy(group_sum<L>(part));
                     const float log_alpha = -beta * (En - E) + prior_log_ratio(pr, vn, vo);
-                    if (lnu[j] < log_alpha) {
+                    if (chain_uniform<L>(lnu[j] < log_alpha)) {
                         E = En;
                         if (!is_bg) {
                             cs.accept_peak(dd, dC, dCN);
