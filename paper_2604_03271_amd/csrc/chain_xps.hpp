@@ -177,7 +177,7 @@ struct XpsChain {
     }
 
     // Energy terms (without (N/2) ln 2 pi) of point p with residual r: ln of the variance
-    // into accl, r^2 over the variance into accq.  A variance <= 0 (energy +inf, R22) makes
+    // into accl, r^2 over the variance into accq.  A variance <= 0 (no likelihood there: energy +inf) makes
     // the sums NaN (the log of a negative number, or -inf + inf, or 0 * inf), which
     // xps_energy maps to +inf once per energy instead of a test per point.
     __device__ __forceinline__ static void noise_term(float r, float yp, const float* hn, float& accl, float& accq) {

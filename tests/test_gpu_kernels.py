@@ -131,7 +131,7 @@ def test_energy_matches_reference(orc, peak, bg, noise, N, K, lanes):
 
 @pytest.mark.parametrize("peak,lanes", [("gauss", 0), ("pvoigt", 64), ("pvoigt", 32)])
 def test_poisson_energy_infinite_where_the_model_is_not_positive(orc, peak, lanes):
-    """Eq. xrd_poisson has no value where a model value is <= 0: energy +inf (R16), on the
+    """Eq. xrd_poisson has no value where a model value is <= 0: energy +inf (zero likelihood), on the
     GPU exactly where the reference gives +inf, finite energies within 1e-5 elsewhere."""
     torch = torch_cuda()
     rng = np.random.default_rng(77)

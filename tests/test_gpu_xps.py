@@ -30,7 +30,7 @@ def _random_theta(rng, spec, K, m):
     return f32(np.array(rows))
 
 
-@pytest.mark.parametrize("n,K", [(300, 2), (840, 7), (1024, 3), (17, 1)])
+@pytest.mark.parametrize("n,K", [(300, 2), (840, 7), (1024, 3), (17, 1), (601, 4)])
 def test_energies_match_reference(orc, n, K):
     torch = torch_cuda()
     spec = W.xps_shirley(index=2, n=n, k_min=K, k_max=K)
@@ -43,6 +43,29 @@ def test_energies_match_reference(orc, n, K):
     opr = orc.Problem(spec)
     ref = np.array([orc.energy(opr, K, r) for r in th]) - _energy_constant(spec)
     assert np.allclose(got, ref, rtol=1e-5, atol=0), np.max(np.abs(got - ref) / np.abs(ref))
+
+
+@pytest.mark.parametrize("n", [840, 601])
+def test_energy_infinite_where_the_variance_is_not_positive(orc, n):
+    """A noise variance s0^2 f + s1^2 f^2 + s2^2 <= 0 at some point (no likelihood there)
+    makes the energy +inf.  A Shirley background of -1000 at both ends puts the model in
+    (-1/s1^2, 0] away from the peaks (every third row); the kernel's NaN-to-+inf mapping must give +inf on exactly those rows, in
+    the unmasked point loops (N = 840: whole padding lanes) and the masked ones (N = 601)."""
+    torch = torch_cuda()
+    K = 3
+    spec = W.xps_shirley(index=2, n=n, k_min=K, k_max=K)
+    say("xps energy +inf", n)
+    th = _random_theta(np.random.default_rng(n), spec, K, 90)
+    th[1::3, -2:] = -1000.0
+    e = torch.zeros(len(th), dtype=torch.float32, device="cuda")
+    native.smc_kernel_energy(native.Problem(spec, K, K), K, dev(th.T.copy(), torch.float32), e)
+    got = e.cpu().numpy().astype(np.float64)
+    opr = orc.Problem(spec)
+    ref = np.array([orc.energy(opr, K, r) for r in th]) - _energy_constant(spec)
+    assert np.all(np.isinf(ref[1::3])) and np.all(np.isfinite(ref[0::3]))
+    assert np.array_equal(np.isposinf(got), np.isposinf(ref)), (got, ref)
+    fin = np.isfinite(ref)
+    assert np.allclose(got[fin], ref[fin], rtol=1e-5, atol=0)
 
 
 def test_init_draws_follow_reference_streams(orc):
