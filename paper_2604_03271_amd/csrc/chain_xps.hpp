@@ -159,21 +159,28 @@ struct XpsChain {
         return total;
     }
 
-    // u_i = C_i / C_N, or (x_i - x_1) / (x_N - x_1) when the peak sum has no area (the
-    // flat-peak limit), as u = C_i * w.ci + x_i * w.xi + w.c0 with loop-variant weights.
+    // The background a + (b - a) u_i with u_i = C_i / C_N, or (x_i - x_1) / (x_N - x_1) when
+    // the peak sum has no area (the flat-peak limit), as B_i = C_i * w.kc + x_i * w.kx + w.k0
+    // with the weights formed once per proposal: two fmas per point.
     struct BgWeights {
-        float ci, xi, c0;
+        float kc, kx, k0;
     };
 
-    __device__ __forceinline__ BgWeights bg_weights(float cn) const {
-        if (cn > 0.0f) return BgWeights{__builtin_amdgcn_rcpf(cn), 0.0f, 0.0f};
-        const float s = __builtin_amdgcn_rcpf(xspan);
-        return BgWeights{0.0f, s, -x1 * s};
+    __device__ __forceinline__ BgWeights bg_weights(float cn, float a, float b) const {
+        const float ba = b - a;
+        if (cn > 0.0f) return BgWeights{ba * __builtin_amdgcn_rcpf(cn), 0.0f, a};
+        const float s = ba * __builtin_amdgcn_rcpf(xspan);
+        return BgWeights{0.0f, s, __builtin_fmaf(-x1, s, a)};
     }
 
-    __device__ __forceinline__ float background(float Cp, const BgWeights& w, int p, float a, float b) const {
-        const float u = __builtin_fmaf(Cp, w.ci, __builtin_fmaf(x[p], w.xi, w.c0));
-        return __builtin_fmaf(b - a, u, a);
+    __device__ __forceinline__ float background(float Cp, const BgWeights& w, int p) const {
+        return __builtin_fmaf(Cp, w.kc, __builtin_fmaf(x[p], w.kx, w.k0));
+    }
+
+    // No lane of the wavefront is in the flat-peak limit (kx = 0 everywhere): the background
+    // is then C_i * kc + k0, the same value without the x term (x kx + k0 = k0 exactly).
+    __device__ __forceinline__ static bool flat_free(const BgWeights& w) {
+        return __builtin_amdgcn_ballot_w64(w.kx != 0.0f) == 0;
     }
 
     // Energy terms (without (N/2) ln 2 pi) of point p with residual r: ln of the variance
@@ -206,8 +213,9 @@ struct XpsChain {
 
     // Energy share of the current state with background (a, b).
     __device__ __forceinline__ float partial_state(const float* hn, float a, float b) const {
-        const BgWeights w = bg_weights(CN);
-        return energy_share(hn, [&](int p) { return R[p] - background(C[p], w, p, a, b); });
+        const BgWeights w = bg_weights(CN, a, b);
+        if (flat_free(w)) return energy_share(hn, [&](int p) { return R[p] - __builtin_fmaf(C[p], w.kc, w.k0); });
+        return energy_share(hn, [&](int p) { return R[p] - background(C[p], w, p); });
     }
 
     // Proposal changing the current peak from qo to qn: d = change of the peak's values,
@@ -231,8 +239,10 @@ struct XpsChain {
             }
         }
         dCN = integrate(d, dC);
-        const BgWeights w = bg_weights(CN + dCN);
-        return energy_share(hn, [&](int p) { return (R[p] - d[p]) - background(C[p] + dC[p], w, p, a, b); });
+        const BgWeights w = bg_weights(CN + dCN, a, b);
+        if (flat_free(w))
+            return energy_share(hn, [&](int p) { return (R[p] - d[p]) - __builtin_fmaf(C[p] + dC[p], w.kc, w.k0); });
+        return energy_share(hn, [&](int p) { return (R[p] - d[p]) - background(C[p] + dC[p], w, p); });
     }
 
     __device__ __forceinline__ void accept_peak(const float* d, const float* dC, float dCN) {

@@ -10,7 +10,10 @@ that difference (sqrt(s_gpu^2/10 + s_oracle^2/10)):
   * |d| <= bound (0.05 nats) as a condition of its own, where the case's particle
     count makes the oracle's standard error small enough for it;
   * the same argmax over the candidate K of the 10-seed means (the posterior mode
-    of p(K | D) under a uniform prior over K, Sec. II.A).
+    of p(K | D) under a uniform prior over K, Sec. II.A), where the oracle's means
+    determine it: its best K leads every other K by more than 3 standard errors of
+    the difference.  Where they do not (some K within 3 SE of the best), the GPU's
+    best K must be one of those statistically tied leaders.
 The oracle's values are stored (tests/golden/oracle_evidences.json, written by a
 script that calls only the oracle); a case whose stored values are missing is
 recomputed live when cheap, else skipped.
@@ -69,8 +72,17 @@ def evidence_parity(orc, name, gpu_of_seed):
     assert np.all(np.abs(d) <= 3 * se), ("beyond 3 SE", d, se)
     if c["bound"] is not None:
         assert np.all(np.abs(d) <= c["bound"]), ("beyond the bound in nats", d, c["bound"])
-    assert np.argmax(g.mean(0)) == np.argmax(o.mean(0)), ("argmax K", g.mean(0), o.mean(0))
+    assert int(np.argmax(g.mean(0))) in oracle_leaders(o), ("argmax K", g.mean(0), o.mean(0))
     return d, se
+
+
+def oracle_leaders(o):
+    """Indices of the K whose oracle 10-seed mean is within 3 standard errors (of the
+    difference) of the best one: the best alone where the oracle's argmax is clear."""
+    mo = o.mean(0)
+    so = o.std(0, ddof=1) / np.sqrt(len(o))
+    b = int(np.argmax(mo))
+    return [k for k in range(len(mo)) if mo[b] - mo[k] <= 3.0 * np.sqrt(so[b] ** 2 + so[k] ** 2)]
 
 
 @pytest.mark.parametrize("name", [n for n in R.CASES if n != "batch_member"])
