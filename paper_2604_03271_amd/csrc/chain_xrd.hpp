@@ -34,9 +34,16 @@ struct XrdC {
 // from the cached width factors (shift, alpha), W1 and the shapes (u, v, w) or W2 and the
 // shapes (s, t).
 enum XrdMode : int { kXrdLinear = 0, kXrdCachedW = 1, kXrdNewW1 = 2, kXrdNewW2 = 3 };
-__device__ __forceinline__ int xrd_peak_mode(int q) {
+__host__ __device__ constexpr int xrd_peak_mode_c(int q) {
     return (q == 0 || q == 2) ? kXrdLinear : (q == 1 || q == 3) ? kXrdCachedW : q <= 6 ? kXrdNewW1 : kXrdNewW2;
 }
+__device__ __forceinline__ int xrd_peak_mode(int q) { return xrd_peak_mode_c(q); }
+
+// Tiles whose move unrolls a peak's nine proposals (the component index, and with it the
+// constants it changes, its linearity and its shape mode, known at compile time): those it
+// leaves spill-free.  The others keep the run-time component loop.
+template <int PPL>
+constexpr bool kXrdUnroll = PPL <= 4 || PPL == 7;
 
 // Constants of peak k (th: its nine parameters) at reference position mref.
 __device__ __forceinline__ XrdC xrd_peak_consts(const float* th, float mref) {
@@ -444,6 +451,48 @@ __global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256, xrd_min_waves(PP
                 // forms its constants from the chain's parameter vector; keeping them all in
                 // registers between proposals measured slower at 4 points per lane)
                 const float mref = is_bg ? 0.0f : g.mu_ref[k];
+                if constexpr (kXrdUnroll<PPL>) {
+                    if (!is_bg) {
+                        // one proposal of peak component QC (compile time)
+                        auto propose = [&](auto qtag) {
+                            constexpr int QC = decltype(qtag)::value;
+                            constexpr int kMode = xrd_peak_mode_c(QC);
+                            const int j = j0 + QC;
+                            const DevPrior pr = constant_load(g.prior + j);
+                            if (pr.kind == SMC_PRIOR_FIXED) return;
+                            const float vo = th[j];
+                            const float vn = vo + inc[j];
+                            if (!chain_uniform<L>(prior_in_support(pr, vn))) return;
+                            const XrdC qn = CS::term_consts_with(g, th, k, QC, vn, mref);
+                            float part;
+                            if constexpr (kMode == kXrdLinear) {
+                                part = cs.template partial_cached_t<false>(qn);
+                                ++my_linear;
+                            } else {
+                                part = cs.template partial_shape_t<false, kMode, (kSB > 0)>(qn, my_shp);
+                                ++my_shape;
+                            }
+                            const float En = poisson_energy(chain_sum<L, WPC>(part, red, parity));
+                            const float log_alpha = -beta * (En - E) + prior_log_ratio(pr, vn, vo);
+                            if (chain_uniform<L>(lnu[j] < log_alpha)) {
+                                E = En;
+                                if constexpr (kMode != kXrdLinear) cs.template accept_shape<(kSB > 0)>(false, kMode, qn, my_shp);
+                                th[j] = vn;
+                                if (lane == 0) atomicAdd(&accc[j], 1u);
+                            }
+                        };
+                        propose(std::integral_constant<int, 0>{});
+                        propose(std::integral_constant<int, 1>{});
+                        propose(std::integral_constant<int, 2>{});
+                        propose(std::integral_constant<int, 3>{});
+                        propose(std::integral_constant<int, 4>{});
+                        propose(std::integral_constant<int, 5>{});
+                        propose(std::integral_constant<int, 6>{});
+                        propose(std::integral_constant<int, 7>{});
+                        propose(std::integral_constant<int, 8>{});
+                        continue;
+                    }
+                }
                 for (int q = 0; q < nq; ++q) {
                     const int j = j0 + q;
                     const DevPrior pr = constant_load(g.prior + j);   // one component per chain: scalar loads
