@@ -375,8 +375,8 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(
     // background) whose constants are qc, from the state tk = th + j0 of that term.  Q >= 0:
     // a peak component known at compile time (the constants are updated field by field);
     // Q == kBgComp: a background coefficient; Q == kAnyComp: a peak component known at run time
-    // (chains narrower than a wavefront, whose code size and registers the unrolled form
-    // would raise).  An accept updates E, qc, the cached shapes and the state.
+    // (16-lane chains, four to a wavefront, where the unrolled form spills).  An accept updates
+    // E, qc, the cached shapes and the state.
     constexpr int kBgComp = -1, kAnyComp = -2;
     bool any_bg = false;
     int nq_any = 0;
@@ -457,7 +457,7 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(
             } else if (kt > 1) {
                 cs.transition(g, th, kt - 1, 0);
             }
-            if constexpr (L == 64) {
+            if constexpr (L >= 32) {
             // the peaks, components in order (Sec. II.B.4); the current term's constants are
             // kept in qc and its shapes in the cache
             for (int k = 0; k < g.K; ++k) {
