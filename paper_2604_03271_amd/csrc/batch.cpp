@@ -141,8 +141,8 @@ struct PoolView {
     size_t cap_groups = 0, cap_work = 0;
 
     void release() {
-        if (d_groups) hipFree(d_groups);
-        if (d_work) hipFree(d_work);
+        if (d_groups) (void)hipFree(d_groups);
+        if (d_work) (void)hipFree(d_work);
         d_groups = nullptr;
         d_work = nullptr;
         cap_groups = cap_work = 0;
@@ -198,12 +198,12 @@ struct PoolView {
             for (int q = buckets[bi].work_off; q < buckets[bi].work_off + buckets[bi].work_cnt; ++q)
                 group_bucket[work[q].group] = static_cast<int>(bi);
         if (groups.size() > cap_groups) {
-            if (d_groups) hipFree(d_groups);
+            if (d_groups) (void)hipFree(d_groups);
             cap_groups = std::max<size_t>(groups.size() * 2, 64);
             if (hipMalloc(&d_groups, sizeof(GroupDesc) * cap_groups) != hipSuccess) return SMC_ENOMEM;
         }
         if (work.size() > cap_work) {
-            if (d_work) hipFree(d_work);
+            if (d_work) (void)hipFree(d_work);
             cap_work = std::max<size_t>(work.size() * 2, 256);
             if (hipMalloc(&d_work, sizeof(MoveWork) * cap_work) != hipSuccess) return SMC_ENOMEM;
         }
@@ -243,7 +243,7 @@ struct PoolView {
         }
         if (scratch.empty()) return SMC_OK;
         if (scratch.size() > cap_scratch) {
-            if (d_scratch) hipFree(d_scratch);
+            if (d_scratch) (void)hipFree(d_scratch);
             cap_scratch = scratch.size() * 2;
             if (hipMalloc(&d_scratch, sizeof(MoveWork) * cap_scratch) != hipSuccess) return SMC_ENOMEM;
         }
@@ -350,18 +350,18 @@ extern "C" smc_status smc_batch_run(const smc_problem* probs, int32_t n, const s
     size_t cap_scratch = 0;
     smc_status status = SMC_OK;
     auto drop_graph = [&]() {
-        if (exec) hipGraphExecDestroy(exec);
-        if (graph) hipGraphDestroy(graph);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
         exec = nullptr;
         graph = nullptr;
     };
     auto cleanup = [&]() {
         drop_graph();
-        hipStreamSynchronize(s);
+        (void)hipStreamSynchronize(s);
         view.release();
-        if (d_scratch) hipFree(d_scratch);
-        if (dmem) hipFree(dmem);
-        if (own) hipStreamDestroy(s);
+        if (d_scratch) (void)hipFree(d_scratch);
+        if (dmem) (void)hipFree(dmem);
+        if (own) (void)hipStreamDestroy(s);
     };
     if (hipMalloc(&dmem, total) != hipSuccess) {
         cleanup();
@@ -635,7 +635,7 @@ extern "C" smc_status smc_server_create(smc_server** out, uint64_t mem_budget_by
         return SMC_EDEVICE;
     }
     if (hipMalloc(&sv->dmem, mem_budget_bytes) != hipSuccess) {
-        hipStreamDestroy(sv->stream);
+        (void)hipStreamDestroy(sv->stream);
         delete sv;
         return SMC_ENOMEM;
     }
@@ -700,10 +700,10 @@ extern "C" void smc_server_destroy(smc_server* sv) {
     }
     sv->cv_work.notify_all();
     if (sv->worker.joinable()) sv->worker.join();
-    hipStreamSynchronize(sv->stream);
+    (void)hipStreamSynchronize(sv->stream);
     sv->view.release();
-    if (sv->d_scratch) hipFree(sv->d_scratch);
-    if (sv->dmem) hipFree(sv->dmem);
-    hipStreamDestroy(sv->stream);
+    if (sv->d_scratch) (void)hipFree(sv->d_scratch);
+    if (sv->dmem) (void)hipFree(sv->dmem);
+    (void)hipStreamDestroy(sv->stream);
     delete sv;
 }

@@ -17,7 +17,7 @@ namespace {
 struct Scratch {
     void* mem = nullptr;
     ~Scratch() {
-        if (mem) hipFree(mem);
+        if (mem) (void)hipFree(mem);
     }
 };
 

@@ -935,11 +935,12 @@ extern "C" smc_status smc_posterior_k(const smc_ctx* c, double* out, int32_t cap
 
 extern "C" void smc_free(smc_ctx* c) {
     if (!c) return;
-    if (c->stream) hipStreamSynchronize(c->stream);
+    // teardown: errors here have nowhere to go
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (hipEvent_t& e : c->ev)
-        if (e) hipEventDestroy(e);
-    if (c->dmem) hipFree(c->dmem);
-    if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+        if (e) (void)hipEventDestroy(e);
+    if (c->dmem) (void)hipFree(c->dmem);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
 

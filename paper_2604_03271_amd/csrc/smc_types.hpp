@@ -106,7 +106,7 @@ struct GroupDesc {
 // of several wavefronts (the cross-wave reduction) needs a few more registers: one wave
 // less where the limit is 4 or 5.
 constexpr int move_min_waves(int peak, int noise, int points, int wpc) {
-    int w;
+    int w = 2;
     if (noise == SMC_NOISE_GAUSS) {
         if (peak == SMC_PEAK_GAUSS) w = points <= 16 ? 5 : (points <= 20 ? 4 : (points <= 24 ? 3 : 2));
         else w = points <= 10 ? 5 : (points <= 16 ? 4 : (points <= 20 ? 3 : 2));

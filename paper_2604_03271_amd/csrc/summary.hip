@@ -199,7 +199,7 @@ smc_status posterior_summary(const float* theta, int d, int P, int n_peaks, int 
         hipMemcpyAsync(q32.data(), d_quant, sizeof(float) * q32.size(), hipMemcpyDeviceToHost, s) != hipSuccess)
         st = SMC_EDEVICE;
     if (hipStreamSynchronize(s) != hipSuccess) st = SMC_EDEVICE;
-    hipFree(buf);
+    (void)hipFree(buf);
     if (st == SMC_OK)
         for (size_t i = 0; i < q32.size(); ++i) quant[i] = q32[i];
     return st;
