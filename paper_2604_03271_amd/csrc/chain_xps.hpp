@@ -54,6 +54,12 @@ __device__ __forceinline__ float chain_scan(float v, float& total) {
     }
 }
 
+// Tiles whose move unrolls a peak's four proposals: 12 and 14 points per lane with 32 or 64
+// lanes per chain, which run two waves per SIMD either way and stay spill-free (elsewhere the
+// unrolled form costs a wave or spills).
+template <int L, int PPL>
+constexpr bool kXpsUnroll = (PPL == 12 || PPL == 14) && L >= 32;
+
 // A chain's energy from its summed shares: NaN (a variance <= 0 somewhere) becomes +inf.
 __device__ __forceinline__ float xps_energy(float e) { return e == e ? e : __builtin_inff(); }
 
@@ -364,6 +370,51 @@ __global__ void __launch_bounds__(256, xps_min_waves(PPL)) k_move_xps(const Grou
                 if (k > 0 && !is_bg) cs.set_shapes(peak_consts<SMC_PEAK_PVOIGT>(th + k * np));
                 const int j0 = is_bg ? jbg : k * np;
                 const int nq = is_bg ? g.nbg : np;
+                if (kXpsUnroll<L, PPL> && !is_bg) {
+                    // a peak's four proposals with the component index known at compile time:
+                    // the changed constant alone is formed anew, and each proposal has one path
+                    const PeakC qo = peak_consts<SMC_PEAK_PVOIGT>(th + j0);
+                    PeakC qc = qo;
+                    auto propose = [&](auto qtag) {
+                        constexpr int Q = decltype(qtag)::value;
+                        constexpr bool kLin = linear_component<SMC_PEAK_PVOIGT>(Q);
+                        const int j = j0 + Q;
+                        const DevPrior pr = constant_load(g.prior + j);
+                        if (pr.kind == SMC_PRIOR_FIXED) return;
+                        const float vo = th[j];
+                        const float vn = vo + inc[j];
+                        if (!chain_uniform<L>(prior_in_support(pr, vn))) return;
+                        float dCN = 0.0f;
+                        const PeakC qn = peak_consts_with<SMC_PEAK_PVOIGT, Q>(qc, th + j0, vn);
+                        const float a = th[jbg], b = th[jbg + 1];
+                        float part;
+                        if constexpr (kLin) {
+                            part = cs.template partial_peak<false>(qc, qn, g.hn, a, b, dd, dC, dCN);
+                            ++my_linear;
+                        } else {
+                            part = cs.template partial_peak<true, (kSB > 0)>(qc, qn, g.hn, a, b, dd, dC, dCN, my_shp);
+                            ++my_shape;
+                        }
+                        const float En = xps_energy(group_sum<L>(part));
+                        const float log_alpha = -beta * (En - E) + prior_log_ratio(pr, vn, vo);
+                        if (chain_uniform<L>(lnu[j] < log_alpha)) {
+                            E = En;
+                            cs.accept_peak(dd, dC, dCN);
+                            if constexpr (!kLin) {
+                                if constexpr (kSB > 0) cs.load_shapes(my_shp);
+                                else cs.set_shapes(qn);
+                            }
+                            qc = qn;
+                            th[j] = vn;
+                            if (lane == 0) atomicAdd(&accc[j], 1u);
+                        }
+                    };
+                    propose(std::integral_constant<int, 0>{});
+                    propose(std::integral_constant<int, 1>{});
+                    propose(std::integral_constant<int, 2>{});
+                    propose(std::integral_constant<int, 3>{});
+                    continue;
+                }
                 for (int q = 0; q < nq; ++q) {
                     const int j = j0 + q;
                     const DevPrior pr = constant_load(g.prior + j);   // one component per chain: scalar loads
