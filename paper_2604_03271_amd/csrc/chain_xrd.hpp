@@ -41,9 +41,11 @@ __device__ __forceinline__ int xrd_peak_mode(int q) { return xrd_peak_mode_c(q);
 
 // Tiles whose move unrolls a peak's nine proposals (the component index, and with it the
 // constants it changes, its linearity and its shape mode, known at compile time): those it
-// leaves spill-free.  The others keep the run-time component loop.
+// leaves spill-free (up to 4 points per lane, 7 and 16) and 20 points per lane, where it spills
+// a few words reloaded once per term and still measured 7-10% faster.  The others keep the
+// run-time component loop.
 template <int PPL>
-constexpr bool kXrdUnroll = PPL <= 4 || PPL == 7;
+constexpr bool kXrdUnroll = PPL <= 4 || PPL == 7 || PPL == 16 || PPL == 20;
 
 // Constants of peak k (th: its nine parameters) at reference position mref.
 __device__ __forceinline__ XrdC xrd_peak_consts(const float* th, float mref) {
