@@ -380,13 +380,12 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(
     constexpr int kBgComp = -1, kAnyComp = -2;
     bool any_bg = false;
     int nq_any = 0;
-    auto propose = [&](auto qtag, int j0, int q, float* tk, PeakC& qc) {
+    auto propose = [&](auto qtag, int j0, int q, float* tk, PeakC& qc, const DevPrior& pr) {
         constexpr int Q = decltype(qtag)::value;
         constexpr bool kBg = Q == kBgComp;
         constexpr bool kAny = Q == kAnyComp;
         const int qi = Q < 0 ? q : Q;
         const int j = j0 + qi;
-        const DevPrior pr = constant_load(g.prior + j);   // the same j in every lane: scalar loads
         if (pr.kind == SMC_PRIOR_FIXED) return;
         const float vo = tk[qi];
         const float vn = vo + inc[j];
@@ -462,12 +461,24 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(
             // kept in qc and its shapes in the cache
             for (int k = 0; k < g.K; ++k) {
                 float* tk = th + k * NP;
+                // the priors (the same component in every lane: scalar loads), each read one
+                // proposal ahead (the first two before the term switch) so that its load
+                // overlaps the work before it
+                const DevPrior* pk = g.prior + k * NP;
+                const DevPrior p0 = constant_load(pk);
+                const DevPrior p1 = constant_load(pk + 1);
                 PeakC qc = peak_consts<PK>(tk);
                 if (k > 0) cs.exclude(false, qc);
-                propose(std::integral_constant<int, 0>{}, k * NP, 0, tk, qc);
-                propose(std::integral_constant<int, 1>{}, k * NP, 1, tk, qc);
-                propose(std::integral_constant<int, 2>{}, k * NP, 2, tk, qc);
-                if constexpr (NP > 3) propose(std::integral_constant<int, 3>{}, k * NP, 3, tk, qc);
+                propose(std::integral_constant<int, 0>{}, k * NP, 0, tk, qc, p0);
+                const DevPrior p2 = constant_load(pk + 2);
+                propose(std::integral_constant<int, 1>{}, k * NP, 1, tk, qc, p1);
+                if constexpr (NP > 3) {
+                    const DevPrior p3 = constant_load(pk + 3);
+                    propose(std::integral_constant<int, 2>{}, k * NP, 2, tk, qc, p2);
+                    propose(std::integral_constant<int, 3>{}, k * NP, 3, tk, qc, p3);
+                } else {
+                    propose(std::integral_constant<int, 2>{}, k * NP, 2, tk, qc, p2);
+                }
                 if (k + 1 < kt) cs.include(false, qc, true);
             }
             // the background coefficients
@@ -475,7 +486,9 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(
                 float* tb = th + g.K * NP;
                 PeakC qb = bg_consts(tb, g.nbg);
                 cs.exclude(true, qb);
-                for (int q = 0; q < g.nbg; ++q) propose(std::integral_constant<int, kBgComp>{}, g.K * NP, q, tb, qb);
+                for (int q = 0; q < g.nbg; ++q)
+                    propose(std::integral_constant<int, kBgComp>{}, g.K * NP, q, tb, qb,
+                            constant_load(g.prior + g.K * NP + q));
             }
             } else {
                 PeakC unused{};
@@ -484,7 +497,8 @@ __global__ void __launch_bounds__(256, move_min_waves(PK, NZ, PPL, WPC)) k_move(
                     const int j0 = k * NP;
                     nq_any = any_bg ? g.nbg : NP;
                     if (k > 0) cs.transition(g, th, k - 1, k);
-                    for (int q = 0; q < nq_any; ++q) propose(std::integral_constant<int, kAnyComp>{}, j0, q, th + j0, unused);
+                    for (int q = 0; q < nq_any; ++q)
+                        propose(std::integral_constant<int, kAnyComp>{}, j0, q, th + j0, unused, constant_load(g.prior + j0 + q));
                 }
             }
             const size_t out = g.waste_free ? (size_t)m * n + t : (size_t)m;
