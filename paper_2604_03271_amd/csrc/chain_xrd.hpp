@@ -118,10 +118,12 @@ struct XrdChain {
 
     __device__ __forceinline__ float peak_w2(const XrdC& q, int p) const {
         // sec(x/2) from an opaque copy of tan(x/2): hoisted out of the sweep loop it would
-        // cost PPL more live registers
+        // cost PPL more live registers.  The hardware square root (about 1 ulp, argument in
+        // [1, 34) here) instead of the correctly rounded sequence, a dozen more instructions
+        // per point of every width evaluation
         float tv = tn[p];
         asm volatile("" : "+v"(tv));
-        const float sec = __builtin_sqrtf(__builtin_fmaf(tv, tv, 1.0f));
+        const float sec = __builtin_amdgcn_sqrtf(__builtin_fmaf(tv, tv, 1.0f));
         const float om = __builtin_fmaf(q.s, sec, q.t * tn[p]);
         return __builtin_amdgcn_rcpf(om * om);
     }
