@@ -76,7 +76,8 @@ __device__ __forceinline__ XrdC xrd_bg_consts(const float* th) {
 // Components of a peak that enter its value linearly (A, r) and of the background (a, r_bg, b).
 __device__ __forceinline__ bool xrd_linear(bool is_bg, int q) { return is_bg ? q != 1 : (q == 0 || q == 2); }
 
-template <int L, int WPC, int PPL>
+// IWL: the move kernel keeps the reciprocal counts in LDS (move_iw_lds_bytes).
+template <int L, int WPC, int PPL, bool IWL = false>
 struct XrdChain {
     static constexpr int LC = L * WPC;
     static constexpr int TPB = LC > 256 ? LC : 256;   // threads per workgroup
@@ -90,6 +91,7 @@ struct XrdChain {
     static constexpr bool kIW = PPL <= 8;
     float x[PPL], tn[PPL], w[PPL];
     float iw[kIW ? PPL : 1];
+    const float* iwl = nullptr;   // IWL: this lane's reciprocal counts in LDS, stride LC
     float D[PPL];
     float S1[PPL], S2[PPL];
     float W1[PPL], W2[PPL];   // width factors of the current term when it is a peak
@@ -106,6 +108,13 @@ struct XrdChain {
             if constexpr (kIW) iw[p] = 1.0f / w[p];
             tn[p] = tanf(ok ? g.x[i] * kHalfRad : 0.0f);
         }
+    }
+
+    // IWL: the reciprocal counts into this lane's LDS area (read back only by this lane).
+    __device__ __forceinline__ void keep_iw(float* dst) {
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) dst[p * LC] = 1.0f / w[p];
+        iwl = dst;
     }
 
     // Width factors of a peak at point p (a = 1): W1 = 1 / Caglioti argument (`bad` collects
@@ -178,6 +187,8 @@ struct XrdChain {
         float iwp;
         if constexpr (kIW) {
             iwp = iw[p];
+        } else if constexpr (IWL) {
+            iwp = iwl[p * LC];
         } else {
             // formed at every use: the empty asm keeps the compiler from hoisting the
             // reciprocals out of the sweep loop into PPL more registers
@@ -389,7 +400,8 @@ __global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256) k_energy_xrd(con
 template <int L, int WPC, int PPL>
 __global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256, xrd_min_waves(PPL))
     k_move_xrd(const GroupDesc* __restrict__ groups, const MoveWork* __restrict__ work) {
-    using CS = XrdChain<L, WPC, PPL>;
+    constexpr int kIB = move_iw_lds_bytes(SMC_PEAK_XRD, PPL, L * WPC);
+    using CS = XrdChain<L, WPC, PPL, (kIB > 0)>;
     constexpr int LC = CS::LC;
     constexpr int TPB = CS::TPB;
     constexpr int CPW = TPB / LC;
@@ -410,8 +422,10 @@ __global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256, xrd_min_waves(PP
     uint32_t* nevals = reinterpret_cast<uint32_t*>(red + 2 * WPC);
     // the proposal's shapes, [chain slot][point][lane] float2, 8-byte aligned after the above
     constexpr int kSB = move_shape_lds_bytes(SMC_PEAK_XRD, SMC_NOISE_POISSON, PPL, LC);
-    float2* my_shp = reinterpret_cast<float2*>(lds + ((kPriorFloats * d + CPW * 3 * d + d + 2 * WPC + 2 + 1) & ~1)) +
-                     (slot * PPL * LC + lane);
+    float* shp_base = lds + ((kPriorFloats * d + CPW * 3 * d + d + 2 * WPC + 2 + 1) & ~1);
+    float2* my_shp = reinterpret_cast<float2*>(shp_base) + (slot * PPL * LC + lane);
+    // the reciprocal counts (kIB > 0), [chain slot][point][lane] float, after the shapes
+    float* my_iw = shp_base + (kSB / 4) * CPW * PPL * LC + (slot * PPL * LC + lane);
 
     const bool active = slot < w.nchains;
     const int m = w.chain0 + slot;
@@ -429,7 +443,10 @@ __global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256, xrd_min_waves(PP
         E = g.start_e[m];
     }
     CS cs;
-    if (active) cs.load_points(g, lane);
+    if (active) {
+        cs.load_points(g, lane);
+        if constexpr (kIB > 0) cs.keep_iw(my_iw);
+    }
     const int kt = g.K + 1;
     int parity = 0;
 

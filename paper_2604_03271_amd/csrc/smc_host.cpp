@@ -244,6 +244,8 @@ size_t move_lds_bytes(const Tile& t, int d, int peak_kind, int noise_kind) {
     size_t b = sizeof(DevPrior) * d + sizeof(float) * (static_cast<size_t>(cpw) * 4 * d + reduce_floats(t));
     const int sb = move_shape_lds_bytes(peak_kind, noise_kind, t.ppl, t.lanes);
     if (sb > 0) b = ((b + 7) & ~static_cast<size_t>(7)) + static_cast<size_t>(sb) * tile_threads(t) * t.ppl;
+    const int ib = move_iw_lds_bytes(peak_kind, t.ppl, t.lanes);
+    if (ib > 0) b = ((b + 7) & ~static_cast<size_t>(7)) + static_cast<size_t>(ib) * tile_threads(t) * t.ppl;
     return b;
 }
 

@@ -138,6 +138,20 @@ constexpr int move_shape_lds_bytes(int peak_kind, int noise_kind, int ppl, int l
     return wgs * threads * ppl * b <= 131072 ? b : 0;
 }
 
+// Bytes of LDS per lane and point where the XRD move kernel keeps the reciprocal of each
+// count from 10 to 16 points per lane (registers hold them up to 8; at 20 the kernel is at
+// its register limit and the LDS reads cost more spills than the v_rcp they replace: 2%
+// slower): 4, or 0 where the workgroups its register budget lets run on one CU would need
+// more than 128 KB for them and the shapes together.
+constexpr int move_iw_lds_bytes(int peak_kind, int ppl, int lanes) {
+    if (peak_kind != SMC_PEAK_XRD || ppl <= 8 || ppl > 16) return 0;
+    const int threads = lanes > 256 ? lanes : 256;
+    const int waves = xrd_min_waves(ppl);
+    const int wgs = waves * 256 / threads > 1 ? waves * 256 / threads : 1;
+    const int sb = move_shape_lds_bytes(peak_kind, SMC_NOISE_POISSON, ppl, lanes);
+    return wgs * threads * ppl * (sb + 4) <= 131072 ? 4 : 0;
+}
+
 // One workgroup of the move / energy kernels: chains [chain0, chain0 + nchains) of a group.
 struct MoveWork {
     int32_t group, chain0, nchains, pad;
