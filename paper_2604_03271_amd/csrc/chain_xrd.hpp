@@ -86,8 +86,8 @@ struct XrdChain {
     // spill); a factor not cached is formed anew by every shape proposal.
     static constexpr bool kCW1 = PPL != 14;
     static constexpr bool kCW2 = PPL <= 10;
-    // The reciprocal of every count (as count_w keeps it) held in registers where they
-    // allow it (up to 12 points per lane); beyond that each deviance term forms it (v_rcp).
+    // The reciprocal of every count (as count_w keeps it) held in registers up to 8 points
+    // per lane, in LDS where IWL says so; otherwise each deviance term forms it (v_rcp).
     static constexpr bool kIW = PPL <= 8;
     float x[PPL], tn[PPL], w[PPL];
     float iw[kIW ? PPL : 1];
