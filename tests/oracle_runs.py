@@ -43,6 +43,27 @@ def _xrd_small():
     return sp
 
 
+def _pv_poisson_small():
+    """The config-3 model (pseudo-Voigt peaks on a constant background, Poisson counts, the
+    same prior forms) at a size the oracle can run at a particle count that makes its evidence
+    tight: N = 512 on 2theta in [10, 30], three peaks, candidates K = 2..4.  Drawn with the
+    workload module's own synthesis helper and a seed of its own."""
+    rng = np.random.default_rng(3100)
+    x = W.f32(10.0 + 20.0 * np.arange(512) / 511.0)
+    A = rng.uniform(1e3, 1e4, 3)
+    mu = rng.uniform(12.0, 28.0, 3)
+    s = rng.uniform(0.1, 0.3, 3)
+    eta = rng.uniform(0.0, 1.0, 3)
+    peaks = [(A[k], mu[k], s[k], eta[k]) for k in range(3)]
+    y = rng.poisson(W._synth(x, "pvoigt", peaks, (100.0, 0.0))).astype(np.float64)
+    ymax, ymin, ymed = float(y.max()), float(y.min()), float(np.median(y))
+    pp = [("gamma", 4.0, 4.0 / (ymax - ymin)), ("uniform", 10.0, 30.0), ("gamma", 2.0, 2.0 / 0.175),
+          ("uniform", 0.0, 1.0)]
+    bgp = [("uniform", 0.5 * ymed, 1.5 * ymed)]
+    return W.Spectrum(x, y, "pvoigt", "const", "poisson", 0.0, pp, bgp, 2, 4,
+                      truth={"K": 3, "peaks": peaks, "bg": (100.0,)}, uid=3100)
+
+
 def _batch_member():
     sp = W.uneven_batch(n_spectra=3, index0=100)[1]
     sp.k_max = 3
@@ -63,6 +84,11 @@ CASES = {
     "pv16_poisson_n4096": dict(spec=lambda: _k_range(W.pvoigt16_poisson_n4096(0), 15, 17), Ks=[15, 16, 17],
                                P=512, n=16, wf=True, seeds=list(range(1, 11)), offset=1000, bound=None,
                                live=False),
+    # the config-3 model at N = 512 (three peaks): 10-seed standard errors near 0.2 nats, where
+    # single full-size config-3 runs at P = 512 spread by hundreds of nats (more where a run
+    # misses a peak)
+    "pv_poisson_n512": dict(spec=_pv_poisson_small, Ks=[2, 3, 4], P=4096, n=16, wf=True, seeds=list(range(1, 11)),
+                            offset=1000, bound=None, live=False),
     "paper_k10": dict(spec=lambda: W.paper_gaussian(10), Ks=[10], P=4000, n=10, wf=True,
                       seeds=list(range(1, 11)), offset=1000, bound=None, live=False),
     "xps_n120": dict(spec=lambda: W.xps_shirley(index=5, n=120, k_min=1, k_max=2), Ks=[1, 2], P=1024, n=10,
