@@ -122,7 +122,7 @@ typedef struct {
     int32_t max_stages;    /* safety cap on tempering stages (e.g. 1000) */
     double ess_frac;       /* rho: target ESS fraction of the bisection (0 < rho < 1; 0.5) */
     uint64_t seed;         /* Philox key together with the problem's uid */
-    int32_t lanes_per_chain; /* 0 = automatic; otherwise 16, 32, 64, 256 or 512 (XRD only) lanes per chain */
+    int32_t lanes_per_chain; /* 0 = automatic; otherwise 16, 32, 64 or 256 lanes per chain, or 128 or 512 (XRD only) */
     int32_t plain;         /* 1 = one K at a time, one kernel per launch (the unbatched comparator) */
     int32_t profile;       /* 1 = time every stage / move launch with HIP events (see smc_profile) */
     void* hip_stream;      /* hipStream_t to run on; NULL = the library's own stream */

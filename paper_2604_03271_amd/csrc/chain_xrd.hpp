@@ -45,7 +45,7 @@ __device__ __forceinline__ int xrd_peak_mode(int q) { return xrd_peak_mode_c(q);
 // a few words reloaded once per term and still measured 7-10% faster.  The others keep the
 // run-time component loop.
 template <int PPL>
-constexpr bool kXrdUnroll = PPL <= 4 || PPL == 7 || PPL == 16 || PPL == 20;
+constexpr bool kXrdUnroll = PPL <= 4 || PPL == 7 || PPL == 8 || PPL == 16 || PPL == 20;
 
 // Constants of peak k (th: its nine parameters) at reference position mref.
 __device__ __forceinline__ XrdC xrd_peak_consts(const float* th, float mref) {
@@ -80,7 +80,7 @@ __device__ __forceinline__ bool xrd_linear(bool is_bg, int q) { return is_bg ? q
 template <int L, int WPC, int PPL, bool IWL = false>
 struct XrdChain {
     static constexpr int LC = L * WPC;
-    static constexpr int TPB = LC > 256 ? LC : 256;   // threads per workgroup
+    static constexpr int TPB = LC > 64 ? LC : 256;   // threads per workgroup (one multi-wavefront chain)
     // Width factors cached in registers: W1 at every tile but 14 points per lane (3 waves
     // per SIMD there: it would spill), W2 up to 10 points per lane (beyond that both would
     // spill); a factor not cached is formed anew by every shape proposal.
@@ -371,7 +371,7 @@ struct XrdChain {
 // Workgroups of TPB threads hold TPB / LC chains; XCD dealing in chunks of 16 chains,
 // whole 64-byte lines of the component-major parameter arrays.
 template <int L, int WPC, int PPL>
-__global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256) k_energy_xrd(const GroupDesc* __restrict__ groups,
+__global__ void __launch_bounds__(L* WPC > 64 ? L * WPC : 256) k_energy_xrd(const GroupDesc* __restrict__ groups,
                                                                              const MoveWork* __restrict__ work) {
     using CS = XrdChain<L, WPC, PPL>;
     constexpr int LC = CS::LC;
@@ -398,7 +398,7 @@ __global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256) k_energy_xrd(con
 
 
 template <int L, int WPC, int PPL>
-__global__ void __launch_bounds__(L* WPC > 256 ? L * WPC : 256, xrd_min_waves(PPL))
+__global__ void __launch_bounds__(L* WPC > 64 ? L * WPC : 256, xrd_min_waves(PPL))
     k_move_xrd(const GroupDesc* __restrict__ groups, const MoveWork* __restrict__ work) {
     constexpr int kIB = move_iw_lds_bytes(SMC_PEAK_XRD, PPL, L * WPC);
     using CS = XrdChain<L, WPC, PPL, (kIB > 0)>;

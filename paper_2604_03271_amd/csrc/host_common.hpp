@@ -23,7 +23,7 @@ struct Tile {
 
 // Threads per workgroup of the move / energy kernels: 256 (several chains of up to 256
 // lanes), or one chain of more lanes.
-inline int tile_threads(const Tile& t) { return t.lanes > 256 ? t.lanes : 256; }
+inline int tile_threads(const Tile& t) { return t.lanes > 64 ? t.lanes : 256; }
 inline int tile_chains_per_wg(const Tile& t) { return tile_threads(t) / t.lanes; }
 
 struct Arena {

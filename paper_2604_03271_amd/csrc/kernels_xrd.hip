@@ -26,6 +26,7 @@ void register_kernels_xrd(KernelTable& t) {
     reg_xrd_list<64, 1, 1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20>(t, 2);
     reg_xrd_list<64, 4, 1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20>(t, 3);
     reg_xrd_list<64, 8, 1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20>(t, 4);
+    reg_xrd_list<64, 2, 1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20>(t, 5);
 }
 
 }  // namespace smc

@@ -119,9 +119,10 @@ smc_status validate(const smc_problem* p, const smc_options* o) {
     if (!(o->ess_frac > 0.0 && o->ess_frac < 1.0)) return SMC_EINVAL;
     if (o->bisect_iters < 1 || o->bisect_iters > 200 || o->max_stages < 1) return SMC_EINVAL;
     if (o->lanes_per_chain != 0 && o->lanes_per_chain != 16 && o->lanes_per_chain != 32 &&
-        o->lanes_per_chain != 64 && o->lanes_per_chain != 256 && o->lanes_per_chain != 512)
+        o->lanes_per_chain != 64 && o->lanes_per_chain != 128 && o->lanes_per_chain != 256 &&
+        o->lanes_per_chain != 512)
         return SMC_EINVAL;
-    if (o->lanes_per_chain == 512 && p->peak_kind != SMC_PEAK_XRD) return SMC_EINVAL;
+    if ((o->lanes_per_chain == 128 || o->lanes_per_chain == 512) && p->peak_kind != SMC_PEAK_XRD) return SMC_EINVAL;
     return SMC_OK;
 }
 
@@ -174,8 +175,8 @@ Tile choose_tile(const smc_problem& p, int64_t chains, int forced_lanes) {
         // one wavefront per chain group, at most 16 points per lane (the Shirley scan runs
         // across the lanes of one wavefront)
         int best = -1;
-        for (int lc = 0; lc < kNumLaneCfg; ++lc) {
-            const int lanes = kLanesOf[lc];
+        for (int li = 0; li < kNumLaneCfg; ++li) {
+            const int lc = kLaneOrder[li], lanes = kLanesOf[lc];
             if (lanes > 64 || (forced_lanes && lanes != forced_lanes)) continue;
             if ((n_points + lanes - 1) / lanes > 16) continue;
             if (!forced_lanes && best >= 0 && kLanesOf[best] >= n_points) break;
@@ -197,19 +198,22 @@ Tile choose_tile(const smc_problem& p, int64_t chains, int forced_lanes) {
     // family has kernels for.
     // The XRD profile holds more per point (tan, y and two shapes) and its move kernel needs
     // several waves per SIMD to hide its transcendental latency: one-wavefront chains only
-    // up to 8 points per lane (3+ waves), then 256 or 512 lanes (measured 11% faster at
-    // N = 1000 than 64 lanes x 16 points at 2 waves).
+    // up to 8 points per lane (3+ waves), then 128 lanes up to 8 points per lane, then 256 or
+    // 512 lanes (whole runs at P = 250000: N = 1000 216 ms at 128 x 8 against 242 at 256 x 4
+    // and 251 at 64 x 16; N = 600 149 ms at 128 x 5 against 172 at 256 x 3; N = 1500, 2000 and
+    // 2560 6-16% slower at 128 lanes than at 256).
     const bool xrd = p.peak_kind == SMC_PEAK_XRD;
     const int max_rows = xrd ? 20 : kPplOf[kNumPpl - 1];
     const int row_limits[3] = {xrd ? 8 : 16, xrd ? 8 : max_rows, max_rows};
     int best = -1;
     for (int cls = 0; cls < 3 && best < 0; ++cls) {
-        for (int lc = 0; lc < kNumLaneCfg; ++lc) {
-            const int lanes = kLanesOf[lc];
+        for (int li = 0; li < kNumLaneCfg; ++li) {
+            const int lc = kLaneOrder[li], lanes = kLanesOf[lc];
             if (forced_lanes ? lanes != forced_lanes : ((cls < 2) != (lanes <= 64))) continue;
             if (!kernels().move[p.peak_kind][p.noise_kind][lc][0]) continue;
             const int rows = (n_points + lanes - 1) / lanes;
             if (rows > (forced_lanes ? max_rows : row_limits[cls])) continue;
+            if (!forced_lanes && lanes == 128 && rows > 8) continue;
             if (!forced_lanes && best >= 0 && kLanesOf[best] >= n_points) break;
             best = lc;
             if (chains * lanes / 64 >= 2048) break;

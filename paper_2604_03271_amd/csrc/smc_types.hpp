@@ -128,7 +128,7 @@ constexpr int xrd_min_waves(int points) { return points <= 6 ? 4 : (points <= 14
 // that the kernel's register budget lets run on one CU would need more than 128 KB of the
 // CU's 160 KB for them (a 256-thread workgroup is one wave per SIMD; 512 threads two).
 constexpr int move_shape_lds_bytes(int peak_kind, int noise_kind, int ppl, int lanes) {
-    const int threads = lanes > 256 ? lanes : 256;
+    const int threads = lanes > 64 ? lanes : 256;
     const int wpc = lanes > 64 ? lanes / 64 : 1;
     const int waves = peak_kind == SMC_PEAK_XRD ? xrd_min_waves(ppl)
                       : noise_kind == SMC_NOISE_HETERO ? xps_min_waves(ppl)
@@ -145,7 +145,7 @@ constexpr int move_shape_lds_bytes(int peak_kind, int noise_kind, int ppl, int l
 // more than 128 KB for them and the shapes together.
 constexpr int move_iw_lds_bytes(int peak_kind, int ppl, int lanes) {
     if (peak_kind != SMC_PEAK_XRD || ppl <= 8 || ppl > 16) return 0;
-    const int threads = lanes > 256 ? lanes : 256;
+    const int threads = lanes > 64 ? lanes : 256;
     const int waves = xrd_min_waves(ppl);
     const int wgs = waves * 256 / threads > 1 ? waves * 256 / threads : 1;
     const int sb = move_shape_lds_bytes(peak_kind, SMC_NOISE_POISSON, ppl, lanes);

@@ -76,7 +76,8 @@ def _init_status(spec, **kw):
     (lambda s: None, {"ess_frac": 1.0}),
     (lambda s: None, {"bisect_iters": 0}),
     (lambda s: None, {"lanes_per_chain": 48}),
-    (lambda s: None, {"lanes_per_chain": 512}),   # 512-lane chains exist for the XRD profile only
+    (lambda s: None, {"lanes_per_chain": 512}),   # 128- and 512-lane chains exist for the XRD profile only
+    (lambda s: None, {"lanes_per_chain": 128}),
     (lambda s: None, {"n_particles": 200_000_000}),   # 12 components x P beyond 32-bit offsets
 ])
 def test_invalid_problems_rejected_on_host(mutate, kw):

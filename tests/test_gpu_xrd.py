@@ -44,8 +44,9 @@ def _thetas(rng, spec, K, m, n_undefined=0):
     return f32(np.array(rows))
 
 
-@pytest.mark.parametrize("n,K,lanes", [(1000, 3, 0), (5120, 3, 0), (1200, 2, 64), (300, 1, 16), (600, 5, 32),
-                                       (4000, 4, 256), (10000, 3, 0), (10240, 2, 512), (3001, 3, 512)])
+@pytest.mark.parametrize("n,K,lanes", [(1000, 3, 0), (1000, 3, 256), (2000, 3, 0), (2500, 2, 128), (500, 2, 64), (5120, 3, 0),
+                                       (1200, 2, 64), (300, 1, 16), (600, 5, 32), (4000, 4, 256), (10000, 3, 0),
+                                       (10240, 2, 512), (3001, 3, 512)])
 def test_energies_match_reference(orc, n, K, lanes):
     torch = torch_cuda()
     spec = _spec(n, K, index=1)
@@ -87,13 +88,15 @@ def test_init_draws_follow_reference_streams(orc):
     assert np.allclose(e[sub][fin], ref[fin], rtol=1e-5, atol=0), np.max(np.abs(e[sub][fin] - ref[fin]) / np.abs(ref[fin]))
 
 
-# tiles: 256 lanes x 4 and 64 x 7 (both width factors cached), 256 x 12, 16 and 20 and 512 x 20
-# (W1 cached), 256 x 14 (neither)
-@pytest.mark.parametrize("n,K,M,nm,wf,beta", [(1000, 3, 128, 4, True, 1e-4), (400, 2, 64, 2, False, 1e-3),
-                                              (5120, 1, 96, 2, True, 1e-2), (10000, 3, 40, 2, True, 1e-4),
-                                              (3000, 2, 64, 2, True, 1e-4), (3500, 2, 64, 2, True, 1e-4),
-                                              (4000, 2, 64, 2, False, 1e-3)])
-def test_move_matches_reference(orc, n, K, M, nm, wf, beta):
+# tiles: 128 lanes x 8, 256 x 4 and 8, 64 x 7 and 8 (both width factors cached), 128 x 16, 256 x
+# 12, 16 and 20 and 512 x 20 (W1 cached), 256 x 14 (neither)
+@pytest.mark.parametrize("n,K,M,nm,wf,beta,lanes", [(1000, 3, 128, 4, True, 1e-4, 0), (1000, 3, 128, 4, True, 1e-4, 256),
+                                                    (400, 2, 64, 2, False, 1e-3, 0), (480, 2, 64, 2, True, 1e-4, 64),
+                                                    (2000, 2, 64, 2, True, 1e-4, 128), (2000, 2, 64, 2, True, 1e-4, 0),
+                                                    (5120, 1, 96, 2, True, 1e-2, 0), (10000, 3, 40, 2, True, 1e-4, 0),
+                                                    (3000, 2, 64, 2, True, 1e-4, 0), (3500, 2, 64, 2, True, 1e-4, 0),
+                                                    (4000, 2, 64, 2, False, 1e-3, 0)])
+def test_move_matches_reference(orc, n, K, M, nm, wf, beta, lanes):
     torch = torch_cuda()
     spec = _spec(n, K, index=4)
     opr = orc.Problem(spec)
@@ -105,13 +108,13 @@ def test_move_matches_reference(orc, n, K, M, nm, wf, beta):
     step = f32(0.1 * start.std(axis=0) + 1e-3)
     d = start.shape[1]
     P = M * nm if wf else M
-    say("xrd move", n, K, M, nm, wf, beta)
+    say("xrd move", n, K, M, nm, wf, beta, lanes)
     out = torch.zeros(d * P, dtype=torch.float32, device="cuda")
     out_e = torch.zeros(P, dtype=torch.float32, device="cuda")
     acc = torch.zeros(d, dtype=torch.int32, device="cuda")
     native.smc_kernel_move(native.Problem(spec, K, K), K, dev(start.T.copy(), torch.float32),
                            dev(startE, torch.float32), nm, wf, beta, 99, 3, dev(step, torch.float32),
-                           out, out_e, acc)
+                           out, out_e, acc, lanes=lanes)
     th_gpu = out.cpu().numpy().reshape(d, P).T.astype(np.float64)
     e_gpu = out_e.cpu().numpy().astype(np.float64)
     sub = np.arange(0, P, max(1, P // 41))
