@@ -45,7 +45,7 @@ __device__ __forceinline__ int xrd_peak_mode(int q) { return xrd_peak_mode_c(q);
 // a few words reloaded once per term and still measured 7-10% faster.  The others keep the
 // run-time component loop.
 template <int PPL>
-constexpr bool kXrdUnroll = PPL <= 4 || PPL == 7 || PPL == 8 || PPL == 14 || PPL == 16 || PPL == 20;
+constexpr bool kXrdUnroll = PPL <= 4 || PPL == 7 || PPL == 8 || PPL == 10 || PPL == 12 || PPL == 14 || PPL == 16 || PPL == 20;
 
 // Constants of peak k (th: its nine parameters) at reference position mref.
 __device__ __forceinline__ XrdC xrd_peak_consts(const float* th, float mref) {
@@ -81,11 +81,12 @@ template <int L, int WPC, int PPL, bool IWL = false>
 struct XrdChain {
     static constexpr int LC = L * WPC;
     static constexpr int TPB = LC > 64 ? LC : 256;   // threads per workgroup (one multi-wavefront chain)
-    // Width factors cached in registers: W1 at every tile but 14 points per lane (3 waves
-    // per SIMD there: it would spill), W2 up to 10 points per lane (beyond that both would
-    // spill); a factor not cached is formed anew by every shape proposal.
-    static constexpr bool kCW1 = PPL != 14;
-    static constexpr bool kCW2 = PPL <= 10;
+    // Width factors cached in registers: W1 at every tile but 12 and 14 points per lane (3
+    // waves per SIMD there: with the unrolled proposals it would spill), W2 up to 8 points
+    // per lane (beyond that it would spill); a factor not cached is formed anew by every
+    // shape proposal.
+    static constexpr bool kCW1 = PPL != 14 && PPL != 12;
+    static constexpr bool kCW2 = PPL <= 8;
     // The reciprocal of every count (as count_w keeps it) held in registers up to 8 points
     // per lane, in LDS where IWL says so; otherwise each deviance term forms it (v_rcp).
     static constexpr bool kIW = PPL <= 8;
