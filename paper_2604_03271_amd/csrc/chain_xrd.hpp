@@ -45,7 +45,7 @@ __device__ __forceinline__ int xrd_peak_mode(int q) { return xrd_peak_mode_c(q);
 // a few words reloaded once per term and still measured 7-10% faster.  The others keep the
 // run-time component loop.
 template <int PPL>
-constexpr bool kXrdUnroll = PPL <= 4 || PPL == 7 || PPL == 8 || PPL == 10 || PPL == 12 || PPL == 14 || PPL == 16 || PPL == 20;
+constexpr bool kXrdUnroll = (PPL <= 8 && PPL != 6) || PPL == 10 || PPL == 12 || PPL == 14 || PPL == 16 || PPL == 20;
 
 // Constants of peak k (th: its nine parameters) at reference position mref.
 __device__ __forceinline__ XrdC xrd_peak_consts(const float* th, float mref) {

@@ -200,8 +200,8 @@ Tile choose_tile(const smc_problem& p, int64_t chains, int forced_lanes) {
     // several waves per SIMD to hide its transcendental latency: one-wavefront chains only
     // up to 8 points per lane (3+ waves), then 128 lanes up to 8 points per lane, then 256 or
     // 512 lanes (whole runs at P = 250000: N = 1000 216 ms at 128 x 8 against 242 at 256 x 4
-    // and 251 at 64 x 16; N = 600 149 ms at 128 x 5 against 172 at 256 x 3; N = 1500, 2000 and
-    // 2560 6-16% slower at 128 lanes than at 256).
+    // and 251 at 64 x 16; N = 600 130 ms at 128 x 5 against 172 at 256 x 3 and 133 at 64 x 10;
+    // N = 1500, 2000 and 2560 6-16% slower at 128 lanes than at 256).
     const bool xrd = p.peak_kind == SMC_PEAK_XRD;
     const int max_rows = xrd ? 20 : kPplOf[kNumPpl - 1];
     const int row_limits[3] = {xrd ? 8 : 16, xrd ? 8 : max_rows, max_rows};
