@@ -173,7 +173,7 @@ smc_status smc_evaluation_kinds(const smc_ctx* ctx, uint64_t* out);
 smc_status smc_profile(const smc_ctx* ctx, double* out);
 
 /* Tile autotuner: runs `stages` (1..64) tempering stages of this problem with every lane
- * count its model family supports and that holds its N points (16, 32, 64, 256; 512 for
+ * count its model family supports and that holds its N points (16, 32, 64, 256; 128 and 512 for
  * XRD), times the move kernel with HIP events, and writes the lane count with the least move
  * time per particle*point evaluation to *lanes_out (and that time, ns, to *ns_per_eval_out
  * if not NULL).  Pass it as options.lanes_per_chain.  Results are cached per process and
