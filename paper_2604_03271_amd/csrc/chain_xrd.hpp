@@ -81,12 +81,12 @@ template <int L, int WPC, int PPL, bool IWL = false>
 struct XrdChain {
     static constexpr int LC = L * WPC;
     static constexpr int TPB = LC > 64 ? LC : 256;   // threads per workgroup (one multi-wavefront chain)
-    // Width factors cached in registers: both up to 8 points per lane, W1 at 10, neither at 12
-    // and 14 (3 waves per SIMD there: with the unrolled proposals they would spill), W2 at 16
+    // Width factors cached in registers: both up to 8 points per lane, neither at 12 and 14 (3
+    // waves per SIMD there: with the unrolled proposals they would spill), W2 alone at 10, 16
     // and 20 (one of the two fits there; W2 is the dearer to form, a square root and two
     // reciprocals against one); a factor not cached is formed anew by every shape proposal.
-    static constexpr bool kCW1 = PPL <= 10;
-    static constexpr bool kCW2 = PPL <= 8 || PPL >= 16;
+    static constexpr bool kCW1 = PPL <= 8;
+    static constexpr bool kCW2 = PPL <= 10 || PPL >= 16;
     // The reciprocal of every count (as count_w keeps it) held in registers up to 8 points
     // per lane, in LDS where IWL says so; otherwise each deviance term forms it (v_rcp).
     static constexpr bool kIW = PPL <= 8;
