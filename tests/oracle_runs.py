@@ -98,6 +98,11 @@ CASES = {
                      wf=True, seeds=list(range(1, 11)), offset=1000, bound=None, live=False),
     "xrd_n60": dict(spec=_xrd_small, Ks=[1, 2], P=512, n=8, wf=False, seeds=list(range(1, 11)), offset=1000,
                     bound=None, live=True),
+    # the artificial XRD pattern at its real size (N = 1000, the free energy at K = 3) with the
+    # benchmark's waste-free n = 10, at a particle count the oracle affords (about 2 minutes of
+    # host time per seed)
+    "xrd_n1000": dict(spec=lambda: W.xrd_powder(n=1000, index=0), Ks=[3], P=2000, n=10, wf=True,
+                      seeds=list(range(1, 11)), offset=1000, bound=None, live=False),
     # one member of a small uneven batch, at the batched configuration's P = 8192
     "batch_member": dict(spec=_batch_member, Ks=[1, 2, 3], P=8192, n=16, wf=True, seeds=list(range(1, 11)),
                          offset=1000, bound=None, live=False),
